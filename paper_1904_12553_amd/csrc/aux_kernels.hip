@@ -1,0 +1,456 @@
+// aux_kernels.hip -- initialisation, FP64 read-back of the macroscopic
+// fields, FP64 conservation / Laplace reductions and a plain copy kernel.
+// None of these run inside the time loop except the diagnostics, which the
+// caller invokes every K steps.
+#include "lattice.h"
+#include "nplbm_internal.h"
+
+namespace nplbm {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ int wrapi(int a, int n) {
+  a %= n;
+  return a < 0 ? a + n : a;
+}
+
+// Neighbour (x + dx, y + dy) of a stencil: periodic in x; in y periodic or a
+// mirror ghost beyond a wall.
+__device__ __forceinline__ int64_t nb(int x, int y, int dx, int dy, int nx, int ny, bool wall) {
+  int xx = wrapi(x + dx, nx);
+  int yy = y + dy;
+  if (wall) {
+    if (yy < 0) yy = -1 - yy;
+    if (yy >= ny) yy = 2 * ny - 1 - yy;
+  } else {
+    yy = wrapi(yy, ny);
+  }
+  return (int64_t)yy * nx + xx;
+}
+
+// eq:N31b on a dense (ny x nx) double plane
+__device__ __forceinline__ double lap9(const double *f, int x, int y, int nx, int ny, bool wall) {
+  const double c = f[(int64_t)y * nx + x];
+  const double ax = f[nb(x, y, 1, 0, nx, ny, wall)] + f[nb(x, y, -1, 0, nx, ny, wall)] +
+                    f[nb(x, y, 0, 1, nx, ny, wall)] + f[nb(x, y, 0, -1, nx, ny, wall)];
+  const double dg = f[nb(x, y, 1, 1, nx, ny, wall)] + f[nb(x, y, -1, 1, nx, ny, wall)] +
+                    f[nb(x, y, 1, -1, nx, ny, wall)] + f[nb(x, y, -1, -1, nx, ny, wall)];
+  return (4.0 * ax + dg - 20.0 * c) / 6.0;
+}
+
+// eq:N31a on a dense (ny x nx) double plane
+__device__ __forceinline__ void grad9(const double *f, int x, int y, int nx, int ny, bool wall,
+                                      double &gx, double &gy) {
+  const double e = f[nb(x, y, 1, 0, nx, ny, wall)], w = f[nb(x, y, -1, 0, nx, ny, wall)];
+  const double n = f[nb(x, y, 0, 1, nx, ny, wall)], s = f[nb(x, y, 0, -1, nx, ny, wall)];
+  const double ne = f[nb(x, y, 1, 1, nx, ny, wall)], nw = f[nb(x, y, -1, 1, nx, ny, wall)];
+  const double se = f[nb(x, y, 1, -1, nx, ny, wall)], sw = f[nb(x, y, -1, -1, nx, ny, wall)];
+  gx = (4.0 * (e - w) + (ne - nw + se - sw)) / 12.0;
+  gy = (4.0 * (n - s) + (ne + nw - se - sw)) / 12.0;
+}
+
+// ---------------------------------------------------------------- init ----
+// phi_i from the volume fractions: eq:N12 inverted with rho_k = rho~_k c_k,
+// phi_i = (rho~_i c_i - rho~_N c_N - b_i) / a_i, which the host passes as
+// phi_i = P1[i] c_i + PN[i] c_N + P0[i].
+struct PhiMap {
+  double P1[kMaxM], PN[kMaxM], P0[kMaxM];
+};
+
+__global__ void k_init_phi(PhiMap pm, int M, const double *c, double *phi, int64_t n) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= n) return;
+  const double cN = c[(int64_t)M * n + id];
+  for (int i = 0; i < M; ++i)
+    phi[(int64_t)i * n + id] = pm.P1[i] * c[(int64_t)i * n + id] + pm.PN[i] * cN + pm.P0[i];
+}
+
+// C_i from phi (eq:N18 line 3 with eq:N17), dense planes
+__global__ void k_chem(const DomDesc *dd, int M, const double *phi, double *C) {
+  const int nx = dd->nx, ny = dd->ny;
+  const int64_t n = (int64_t)nx * ny;
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= n) return;
+  const int x = (int)(id % nx), y = (int)(id / nx);
+  const bool wall = dd->wall != 0;
+  const Consts<double> &K = dd->cd;
+  const int N = M + 1;
+  double ph[kMaxM], lp[kMaxM], wv[kMaxN];
+  for (int i = 0; i < M; ++i) {
+    ph[i] = phi[(int64_t)i * n + id];
+    lp[i] = lap9(phi + (int64_t)i * n, x, y, nx, ny, wall);
+  }
+  for (int k = 0; k < N; ++k) {
+    double ck = K.ca[k];
+    for (int i = 0; i < M; ++i) ck += K.cA[k][i] * ph[i];
+    wv[k] = ck * (1.0 - ck) * (1.0 - 2.0 * ck);
+  }
+  for (int i = 0; i < M; ++i) {
+    double Ci = 0.0;
+    for (int j = 0; j < M; ++j) Ci -= K.lam[i][j] * lp[j];
+    for (int k = 0; k < N; ++k) Ci += K.KH[k][i] * wv[k];
+    C[(int64_t)i * n + id] = Ci;
+  }
+}
+
+// Equilibria (eq:25 with p = 0, eq:N25) written in pull layout: the value
+// that node x must pull in direction k is stored where the step kernel
+// reads it, i.e. at x - c_k, or in the opposite direction at x itself when
+// x - c_k lies beyond a wall.
+template <typename Real>
+__global__ void k_init_dist(const DomDesc *dd, int M, const double *phi, const double *C,
+                            const double *u) {
+  const int nx = dd->nx, ny = dd->ny, pitch = dd->pitch;
+  const int64_t n = (int64_t)nx * ny;
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= n) return;
+  const int x = (int)(id % nx), y = (int)(id / nx);
+  const bool wall = dd->wall != 0;
+  const Consts<double> &K = dd->cd;
+  const int64_t plane = dd->plane;
+  Real *h = static_cast<Real *>(dd->h[dd->parity0]);
+  Real *g = static_cast<Real *>(dd->g[dd->parity0]);
+  Real *pv = static_cast<Real *>(dd->prev);
+  const double ux = u ? u[id] : 0.0, uy = u ? u[n + id] : 0.0;
+  double rho = K.ra;
+  for (int i = 0; i < M; ++i) rho += K.rA[i] * phi[(int64_t)i * n + id];
+  const double usq = ux * ux + uy * uy;
+  const int64_t self = (int64_t)y * pitch + x;
+  for (int k = 0; k < 9; ++k) {
+    const int cx = cxk(k), cy = cyk(k);
+    const int ys = y - cy;
+    int64_t off;
+    int kk = k;
+    if (wall && (ys < 0 || ys >= ny)) {
+      kk = oppk(k);
+      off = self;
+    } else {
+      off = (int64_t)wrapi(ys, ny) * pitch + wrapi(x - cx, nx);
+    }
+    const double w = wk<double>(k);
+    const double cu = cx * ux + cy * uy;
+    for (int i = 0; i < M; ++i) {
+      const double ph = phi[(int64_t)i * n + id], Ci = C[(int64_t)i * n + id];
+      const double ec = K.eta_i[i] * Ci;
+      const double v = (k == 0) ? ph + (w - 1.0) * ec
+                                : w * ec + w * 3.0 * (cx * ph * ux + cy * ph * uy);
+      h[(int64_t)(i * 9 + kk) * plane + off] = (Real)v;
+    }
+    if (k > 0) {
+      const double v = rho * w * (3.0 * cu + 4.5 * cu * cu - 1.5 * usq);  // p = 0
+      g[(int64_t)(kk - 1) * plane + off] = (Real)v;
+    }
+  }
+  for (int i = 0; i < M; ++i) pv[(int64_t)i * plane + self] = (Real)phi[(int64_t)i * n + id];
+  pv[(int64_t)M * plane + self] = (Real)ux;
+  pv[(int64_t)(M + 1) * plane + self] = (Real)uy;
+}
+
+// --------------------------------------------------------------- macro ----
+// phi (pull + eq:N28), c_k, rho in FP64 from the stored populations
+template <typename Real>
+__global__ void k_macro_phi(const DomDesc *dd, int M, int parity, double *phi, double *rho,
+                            double *cout) {
+  const int nx = dd->nx, ny = dd->ny, pitch = dd->pitch;
+  const int64_t n = (int64_t)nx * ny;
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= n) return;
+  const int x = (int)(id % nx), y = (int)(id / nx);
+  const bool wall = dd->wall != 0;
+  const int64_t plane = dd->plane;
+  const Real *h = static_cast<const Real *>(dd->h[parity]);
+  const Consts<double> &K = dd->cd;
+  const int N = M + 1;
+  double ph[kMaxM];
+  for (int i = 0; i < M; ++i) ph[i] = 0.0;
+  for (int k = 0; k < 9; ++k) {
+    const int cx = cxk(k), cy = cyk(k);
+    const int ys = y - cy;
+    int64_t off;
+    int kk = k;
+    if (wall && (ys < 0 || ys >= ny)) {
+      kk = oppk(k);
+      off = (int64_t)y * pitch + x;
+    } else {
+      off = (int64_t)wrapi(ys, ny) * pitch + wrapi(x - cx, nx);
+    }
+    for (int i = 0; i < M; ++i) ph[i] += (double)h[(int64_t)(i * 9 + kk) * plane + off];
+  }
+  double r = K.ra;
+  for (int i = 0; i < M; ++i) {
+    phi[(int64_t)i * n + id] = ph[i];
+    r += K.rA[i] * ph[i];
+  }
+  rho[id] = r;
+  if (cout)
+    for (int k = 0; k < N; ++k) {
+      double ck = K.ca[k];
+      for (int i = 0; i < M; ++i) ck += K.cA[k][i] * ph[i];
+      cout[(int64_t)k * n + id] = ck;
+    }
+}
+
+// u (eq:N22_1) and p (eq:N23) in FP64
+template <typename Real>
+__global__ void k_macro_up(const DomDesc *dd, int M, int parity, const double *phi,
+                           const double *rho, const double *C, double *uout, double *pout) {
+  const int nx = dd->nx, ny = dd->ny, pitch = dd->pitch;
+  const int64_t n = (int64_t)nx * ny;
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= n) return;
+  const int x = (int)(id % nx), y = (int)(id / nx);
+  const bool wall = dd->wall != 0;
+  const int64_t plane = dd->plane;
+  const Real *g = static_cast<const Real *>(dd->g[parity]);
+  const Consts<double> &K = dd->cd;
+  double Fx = 0.0, Fy = 0.0, grx = 0.0, gry = 0.0;
+  for (int i = 0; i < M; ++i) {
+    double gx, gy;
+    grad9(phi + (int64_t)i * n, x, y, nx, ny, wall, gx, gy);
+    const double Ci = C[(int64_t)i * n + id];
+    Fx += Ci * gx;
+    Fy += Ci * gy;
+    grx += K.rA[i] * gx;
+    gry += K.rA[i] * gy;
+  }
+  const double r = rho[id];
+  Fx += r * K.gx;
+  Fy += r * K.gy;
+  double gk[9];
+  gk[0] = 0.0;
+  for (int k = 1; k < 9; ++k) {
+    const int cx = cxk(k), cy = cyk(k);
+    const int ys = y - cy;
+    int64_t off;
+    int kk = k;
+    if (wall && (ys < 0 || ys >= ny)) {
+      kk = oppk(k);
+      off = (int64_t)y * pitch + x;
+    } else {
+      off = (int64_t)wrapi(ys, ny) * pitch + wrapi(x - cx, nx);
+    }
+    gk[k] = (double)g[(int64_t)(kk - 1) * plane + off];
+  }
+  double mx = 0.0, my = 0.0, sg = 0.0;
+  for (int k = 1; k < 9; ++k) {
+    mx += cxk(k) * gk[k];
+    my += cyk(k) * gk[k];
+    sg += gk[k];
+  }
+  const double ux = (mx + 0.5 * Fx) / r, uy = (my + 0.5 * Fy) / r;
+  if (uout) {
+    uout[id] = ux;
+    uout[n + id] = uy;
+  }
+  if (pout) pout[id] = 0.6 * (sg + 0.5 * (ux * grx + uy * gry) - (2.0 / 3.0) * r * (ux * ux + uy * uy));
+}
+
+// ---------------------------------------------------------- reductions ----
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Per-block partial sums of each c_k, max |sum_k c_k - 1| and non-finite
+// count; a block strides over the field so the result does not depend on
+// scheduling.  partials[b * (N + 2) + q].
+__global__ void k_diag_partial(const double *c, int N, int64_t n, double *partials) {
+  __shared__ double red[kThreads / 64][kMaxN + 2];
+  double acc[kMaxN + 2];
+  for (int q = 0; q < N + 2; ++q) acc[q] = 0.0;
+  for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < n;
+       id += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    bool bad = false;
+    for (int k = 0; k < N; ++k) {
+      const double v = c[(int64_t)k * n + id];
+      bad |= !isfinite(v);
+      acc[k] += v;
+      s += v;
+    }
+    acc[N] = fmax(acc[N], fabs(s - 1.0));
+    acc[N + 1] += bad ? 1.0 : 0.0;
+  }
+  const int wv = threadIdx.x / 64, ln = threadIdx.x & 63;
+  for (int q = 0; q < N + 2; ++q) {
+    const double r = (q == N) ? wave_max(acc[q]) : wave_sum(acc[q]);
+    if (ln == 0) red[wv][q] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 0; q < N + 2; ++q) {
+      double r = red[0][q];
+      for (int w = 1; w < kThreads / 64; ++w) r = (q == N) ? fmax(r, red[w][q]) : r + red[w][q];
+      partials[(int64_t)blockIdx.x * (N + 2) + q] = r;
+    }
+  }
+}
+
+__global__ void k_diag_final(const double *partials, int nq, int nblk, const int *ismax,
+                             double *out) {
+  const int q = threadIdx.x;
+  if (q >= nq) return;
+  double r = 0.0;
+  for (int b = 0; b < nblk; ++b) {
+    const double v = partials[(int64_t)b * nq + q];
+    r = ismax[q] ? fmax(r, v) : r + v;
+  }
+  out[q] = r;
+}
+
+// Laplace: sums and counts of p inside r <= r_in and outside r >= r_out
+__global__ void k_laplace_partial(const double *p, int nx, int ny, double xc, double yc,
+                                  double r_in, double r_out, double *partials) {
+  __shared__ double red[kThreads / 64][4];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t n = (int64_t)nx * ny;
+  for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < n;
+       id += (int64_t)gridDim.x * blockDim.x) {
+    const double x = (double)(id % nx), y = (double)(id / nx);
+    const double r = sqrt((x - xc) * (x - xc) + (y - yc) * (y - yc));
+    if (r <= r_in) {
+      acc[0] += p[id];
+      acc[1] += 1.0;
+    } else if (r >= r_out) {
+      acc[2] += p[id];
+      acc[3] += 1.0;
+    }
+  }
+  const int wv = threadIdx.x / 64, ln = threadIdx.x & 63;
+  for (int q = 0; q < 4; ++q) {
+    const double r = wave_sum(acc[q]);
+    if (ln == 0) red[wv][q] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 4; ++q) {
+      double r = 0.0;
+      for (int w = 0; w < kThreads / 64; ++w) r += red[w][q];
+      partials[(int64_t)blockIdx.x * 4 + q] = r;
+    }
+}
+
+__global__ void k_laplace_final(const double *partials, int nblk, double *out) {
+  if (threadIdx.x != 0) return;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = 0; b < nblk; ++b)
+    for (int q = 0; q < 4; ++q) a[q] += partials[(int64_t)b * 4 + q];
+  out[0] = (a[1] > 0.0 && a[3] > 0.0) ? a[0] / a[1] - a[2] / a[3] : 0.0;
+}
+
+__global__ void k_copy16(uint4 *__restrict__ dst, const uint4 *__restrict__ src, int64_t n16) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+__global__ void k_copy1(unsigned char *dst, const unsigned char *src, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+__constant__ int c_diag_ismax[kMaxN + 2];
+
+}  // namespace
+
+static int blocks_for(int64_t n) { return (int)((n + kThreads - 1) / kThreads); }
+
+hipError_t launch_init(const DomDesc *dd_dev, const DomDesc &dd, int precision,
+                       const double *P1, const double *PN, const double *P0,
+                       const double *c_dev, const double *u_dev, double *phi_tmp,
+                       double *C_tmp, hipStream_t st) {
+  const int M = dd.N - 1;
+  const int64_t n = (int64_t)dd.nx * dd.ny;
+  PhiMap pm;
+  for (int i = 0; i < kMaxM; ++i) {
+    pm.P1[i] = i < M ? P1[i] : 0.0;
+    pm.PN[i] = i < M ? PN[i] : 0.0;
+    pm.P0[i] = i < M ? P0[i] : 0.0;
+  }
+  const int nb = blocks_for(n);
+  hipLaunchKernelGGL(k_init_phi, dim3(nb), dim3(kThreads), 0, st, pm, M, c_dev, phi_tmp, n);
+  hipLaunchKernelGGL(k_chem, dim3(nb), dim3(kThreads), 0, st, dd_dev, M, phi_tmp, C_tmp);
+  if (precision == 64)
+    hipLaunchKernelGGL(k_init_dist<double>, dim3(nb), dim3(kThreads), 0, st, dd_dev, M,
+                       phi_tmp, C_tmp, u_dev);
+  else
+    hipLaunchKernelGGL(k_init_dist<float>, dim3(nb), dim3(kThreads), 0, st, dd_dev, M,
+                       phi_tmp, C_tmp, u_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_macro(const DomDesc *dd_dev, const DomDesc &dd, int precision, int parity,
+                        double *phi, double *rho, double *C, double *c_out, double *u_out,
+                        double *p_out, hipStream_t st) {
+  const int M = dd.N - 1;
+  const int64_t n = (int64_t)dd.nx * dd.ny;
+  const int nb = blocks_for(n);
+  if (precision == 64)
+    hipLaunchKernelGGL(k_macro_phi<double>, dim3(nb), dim3(kThreads), 0, st, dd_dev, M, parity,
+                       phi, rho, c_out);
+  else
+    hipLaunchKernelGGL(k_macro_phi<float>, dim3(nb), dim3(kThreads), 0, st, dd_dev, M, parity,
+                       phi, rho, c_out);
+  if (!u_out && !p_out) return hipGetLastError();
+  hipLaunchKernelGGL(k_chem, dim3(nb), dim3(kThreads), 0, st, dd_dev, M, phi, C);
+  if (precision == 64)
+    hipLaunchKernelGGL(k_macro_up<double>, dim3(nb), dim3(kThreads), 0, st, dd_dev, M, parity,
+                       phi, rho, C, u_out, p_out);
+  else
+    hipLaunchKernelGGL(k_macro_up<float>, dim3(nb), dim3(kThreads), 0, st, dd_dev, M, parity,
+                       phi, rho, C, u_out, p_out);
+  return hipGetLastError();
+}
+
+int diag_blocks(int64_t n) {
+  int64_t b = (n + kThreads - 1) / kThreads;
+  return (int)(b < 1024 ? (b < 1 ? 1 : b) : 1024);
+}
+
+hipError_t launch_diag(const double *c, int N, int64_t n, double *partials, int nblk,
+                       double *out, hipStream_t st) {
+  int ismax[kMaxN + 2] = {0};
+  ismax[N] = 1;
+  hipError_t e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_diag_ismax), ismax, sizeof(ismax), 0,
+                                        hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_diag_partial, dim3(nblk), dim3(kThreads), 0, st, c, N, n, partials);
+  int *dismax = nullptr;
+  e = hipGetSymbolAddress((void **)&dismax, HIP_SYMBOL(c_diag_ismax));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, st, partials, N + 2, nblk, dismax, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_laplace(const double *p, int nx, int ny, double xc, double yc, double r_in,
+                          double r_out, double *partials, int nblk, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_laplace_partial, dim3(nblk), dim3(kThreads), 0, st, p, nx, ny, xc, yc,
+                     r_in, r_out, partials);
+  hipLaunchKernelGGL(k_laplace_final, dim3(1), dim3(64), 0, st, partials, nblk, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(void *dst, const void *src, size_t nbytes, hipStream_t st) {
+  const bool aligned = (((uintptr_t)dst | (uintptr_t)src) & 15) == 0;
+  const int64_t n16 = aligned ? (int64_t)(nbytes / 16) : 0;
+  if (n16 > 0) {
+    int64_t nb = (n16 + kThreads - 1) / kThreads;
+    if (nb > 8192) nb = 8192;
+    hipLaunchKernelGGL(k_copy16, dim3((unsigned)nb), dim3(kThreads), 0, st,
+                       static_cast<uint4 *>(dst), static_cast<const uint4 *>(src), n16);
+  }
+  const int64_t rest = (int64_t)nbytes - n16 * 16;
+  if (rest > 0)
+    hipLaunchKernelGGL(k_copy1, dim3((unsigned)((rest + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, st, static_cast<unsigned char *>(dst) + n16 * 16,
+                       static_cast<const unsigned char *>(src) + n16 * 16, rest);
+  return hipGetLastError();
+}
+
+}  // namespace nplbm

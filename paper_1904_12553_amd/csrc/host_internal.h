@@ -1,0 +1,46 @@
+// host_internal.h -- host-side helpers shared by the C-ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "nplbm.h"
+#include "nplbm_internal.h"
+
+namespace nplbm {
+
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+void clear_error();
+const char *last_error();
+
+// Everything derived on the host from nplbm_params.
+struct Derived {
+  int N = 0;
+  double eta = 0, beta2 = 0, K = 0;
+  std::vector<double> lam;         // (N-1) x (N-1)
+  double P1[kMaxM] = {0}, PN[kMaxM] = {0}, P0[kMaxM] = {0};  // eq:N12 inverse
+  Consts<double> cd;
+  Consts<float> cf;
+};
+int derive(const nplbm_params *p, Derived &d);
+
+// Byte offsets of every device buffer of one domain inside its allocation.
+struct Layout {
+  int pitch = 0;
+  int64_t plane = 0;
+  size_t h[2] = {0, 0}, g[2] = {0, 0}, prev = 0, state_end = 0;
+  size_t desc = 0, strips = 0;
+  int nstrips = 0;
+  size_t phi = 0, rho = 0, C = 0, c = 0, u = 0, p = 0;
+  int nblk = 0;
+  size_t partials = 0, out = 0;
+  size_t total = 0;
+};
+Layout plan_layout(const nplbm_params *p);
+
+void build_strips(int nx, int ny, int dom, std::vector<StripDesc> &out, int target = 0);
+void xcd_order(std::vector<StripDesc> &s);
+
+}  // namespace nplbm

@@ -1,0 +1,105 @@
+// nplbm_internal.h -- device-side data structures shared by the host
+// library and the gfx950 kernels (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nplbm {
+
+constexpr int kMaxN = 8;          // phases
+constexpr int kMaxM = kMaxN - 1;  // order parameters
+constexpr int kBW = 64;           // lanes per strip row (one wave)
+constexpr int kTX = kBW - 4;      // interior columns per strip (2-column halo each side)
+constexpr int kRows = 2;          // rows per marching iteration (one wave per row)
+constexpr int kStepThreads = kBW * kRows;
+
+// Per-domain constants, folded on the host from the paper's closure so that
+// every per-node quantity is an affine map or a short dot product:
+//   c_k   = ca[k]  + sum_i cA[k][i] phi_i        (eq:N18, lines 1-2)
+//   rho   = ra     + sum_i rA[i]    phi_i        (eq:N18 line 5 / eq:N29)
+//   mu    = ma     + sum_i mA[i]    phi_i        (mu = sum_k mu~_k c_k)
+//   C_i   = -sum_j lam[i][j] lap phi_j + sum_k KH[k][i] w_k,
+//           w_k = c_k (1 - c_k) (1 - 2 c_k)       (eq:N18 line 3 with eq:N17)
+//   grad rho = sum_i rA[i] grad phi_i             (linearity of eq:N31a)
+//   J~    = sum_i Jc[i] grad C_i                  (eq:N18 line 4)
+template <typename Real>
+struct Consts {
+  Real ca[kMaxN];
+  Real cA[kMaxN][kMaxM];
+  Real ra, ma;
+  Real rA[kMaxM];
+  Real mA[kMaxM];
+  Real lam[kMaxM][kMaxM];
+  Real KH[kMaxN][kMaxM];
+  Real Jc[kMaxM];
+  Real eta_i[kMaxM];     // eq:N30
+  Real itau_i[kMaxM];    // 1 / tau_i
+  Real src_i[kMaxM];     // 1 - 1 / (2 tau_i), eq:N26
+  Real gx, gy;
+  Real itau_g, src_g, theta_g;  // used when tau_g is constant
+  int32_t const_tau;
+  int32_t pad_;
+};
+
+// One resident domain as the kernels see it.
+struct DomDesc {
+  void *h[2];        // CH populations, [(N-1)][9][ny][pitch], ping-pong
+  void *g[2];        // NS populations k = 1..8, [8][ny][pitch], ping-pong
+  void *prev;        // previous phi_i (N-1 planes) and u (2 planes), in place
+  int64_t plane;     // elements per plane = ny * pitch
+  int32_t nx, ny, pitch, wall;
+  int32_t N;
+  int32_t parity0;   // buffer holding the current state at substep 0
+  int32_t steps_left;  // substeps >= steps_left do nothing
+  int32_t pad_;
+  Consts<double> cd;
+  Consts<float> cf;
+};
+
+// One strip of the marching step kernel: interior columns [x0, x0 + kTX)
+// clipped to nx, interior rows [y0, y1), marched upward (dir = +1) or
+// downward (dir = -1).  dom < 0 marks an empty slot.
+struct StripDesc {
+  int32_t dom;
+  int32_t x0, y0, y1;
+  int32_t dir;
+  int32_t pad_[3];
+};
+
+struct StepArgs {
+  const StripDesc *strips;
+  const DomDesc *doms;
+  int32_t substep;
+  int32_t pad_;
+};
+
+// Launchers (defined in the .hip files).  All are asynchronous on `st`.
+hipError_t launch_step(int N, int precision, const StepArgs &a, int nblocks, hipStream_t st);
+
+// Initialisation: phi (double, (N-1) planes of nx*ny) is computed from c,
+// then C from phi, then h^eq / g^eq written in pull layout.
+// phi_i = P1[i] c_i + PN[i] c_N + P0[i] (eq:N12 inverted).
+hipError_t launch_init(const DomDesc *dd_dev, const DomDesc &dd, int precision,
+                       const double *P1, const double *PN, const double *P0,
+                       const double *c_dev, const double *u_dev, double *phi_tmp,
+                       double *C_tmp, hipStream_t st);
+
+// Macroscopic fields in FP64 from the current state: phi (N-1), c (N), rho,
+// C (N-1), u (2), p.  Any output plane pointer group may be null.
+// Dense planes (nx*ny); u/p need the C scratch.
+hipError_t launch_macro(const DomDesc *dd_dev, const DomDesc &dd, int precision, int parity,
+                        double *phi, double *rho, double *C, double *c_out, double *u_out,
+                        double *p_out, hipStream_t st);
+
+// FP64 reductions over the c fields (N planes): per-phase sums, max
+// |sum c - 1|, non-finite count.  partials must hold nblk*(N+2) doubles.
+int diag_blocks(int64_t n);
+hipError_t launch_diag(const double *c, int N, int64_t n, double *partials, int nblk,
+                       double *out, hipStream_t st);
+hipError_t launch_laplace(const double *p, int nx, int ny, double xc, double yc,
+                          double r_in, double r_out, double *partials, int nblk,
+                          double *out, hipStream_t st);
+hipError_t launch_copy(void *dst, const void *src, size_t nbytes, hipStream_t st);
+
+}  // namespace nplbm
