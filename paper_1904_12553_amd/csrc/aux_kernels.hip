@@ -98,7 +98,8 @@ __global__ void k_chem(const DomDesc *dd, int M, const double *phi, double *C) {
 // Equilibria (eq:25 with p = 0, eq:N25) written in pull layout: the value
 // that node x must pull in direction k is stored where the step kernel
 // reads it, i.e. at x - c_k, or in the opposite direction at x itself when
-// x - c_k lies beyond a wall.
+// x - c_k lies beyond a wall.  The k = 0 slot holds the deviation of h_0
+// from the stored phi (prev), as the step kernel expects.
 template <typename Real>
 __global__ void k_init_dist(const DomDesc *dd, int M, const double *phi, const double *C,
                             const double *u) {
@@ -112,7 +113,7 @@ __global__ void k_init_dist(const DomDesc *dd, int M, const double *phi, const d
   const int64_t plane = dd->plane;
   Real *h = static_cast<Real *>(dd->h[dd->parity0]);
   Real *g = static_cast<Real *>(dd->g[dd->parity0]);
-  Real *pv = static_cast<Real *>(dd->prev);
+  Real *pv = static_cast<Real *>(dd->prev[dd->parity0]);
   const double ux = u ? u[id] : 0.0, uy = u ? u[n + id] : 0.0;
   double rho = K.ra;
   for (int i = 0; i < M; ++i) rho += K.rA[i] * phi[(int64_t)i * n + id];
@@ -134,7 +135,8 @@ __global__ void k_init_dist(const DomDesc *dd, int M, const double *phi, const d
     for (int i = 0; i < M; ++i) {
       const double ph = phi[(int64_t)i * n + id], Ci = C[(int64_t)i * n + id];
       const double ec = K.eta_i[i] * Ci;
-      const double v = (k == 0) ? ph + (w - 1.0) * ec
+      // k = 0: h_0^eq - phi_stored with phi_stored = (Real)phi
+      const double v = (k == 0) ? (ph - (double)(Real)ph) + (w - 1.0) * ec
                                 : w * ec + w * 3.0 * (cx * ph * ux + cy * ph * uy);
       h[(int64_t)(i * 9 + kk) * plane + off] = (Real)v;
     }
@@ -161,10 +163,12 @@ __global__ void k_macro_phi(const DomDesc *dd, int M, int parity, double *phi, d
   const bool wall = dd->wall != 0;
   const int64_t plane = dd->plane;
   const Real *h = static_cast<const Real *>(dd->h[parity]);
+  const Real *pv = static_cast<const Real *>(dd->prev[parity]);
   const Consts<double> &K = dd->cd;
   const int N = M + 1;
   double ph[kMaxM];
-  for (int i = 0; i < M; ++i) ph[i] = 0.0;
+  // phi_i = phi_prev + (h_0 - phi_prev) + sum_{k>=1} h_k (eq:N28)
+  for (int i = 0; i < M; ++i) ph[i] = (double)pv[(int64_t)i * plane + (int64_t)y * pitch + x];
   for (int k = 0; k < 9; ++k) {
     const int cx = cxk(k), cy = cyk(k);
     const int ys = y - cy;

@@ -30,7 +30,7 @@ int derive(const nplbm_params *p, Derived &d);
 struct Layout {
   int pitch = 0;
   int64_t plane = 0;
-  size_t h[2] = {0, 0}, g[2] = {0, 0}, prev = 0, state_end = 0;
+  size_t h[2] = {0, 0}, g[2] = {0, 0}, prev[2] = {0, 0}, state_end = 0;
   size_t desc = 0, strips = 0;
   int nstrips = 0;
   size_t phi = 0, rho = 0, C = 0, c = 0, u = 0, p = 0;

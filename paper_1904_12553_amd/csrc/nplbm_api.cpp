@@ -187,7 +187,8 @@ int nplbm_create(const nplbm_params *p, void *stream, void *device_mem, size_t d
     D.h[b] = d->base + d->L.h[b];
     D.g[b] = d->base + d->L.g[b];
   }
-  D.prev = d->base + d->L.prev;
+  D.prev[0] = d->base + d->L.prev[0];
+  D.prev[1] = d->base + d->L.prev[1];
   D.plane = d->L.plane;
   D.nx = p->nx;
   D.ny = p->ny;
@@ -378,7 +379,8 @@ int nplbm_get_state(nplbm_domain *d, void *host, int64_t *time_out) {
   if (e == hipSuccess)
     e = hipMemcpyAsync(o + hb, d->base + d->L.g[par], gb, hipMemcpyDeviceToHost, d->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(o + hb + gb, d->base + d->L.prev, pb, hipMemcpyDeviceToHost, d->stream);
+    e = hipMemcpyAsync(o + hb + gb, d->base + d->L.prev[par], pb, hipMemcpyDeviceToHost,
+                       d->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(d->stream);
   if (e != hipSuccess) return hip_fail(e, "state copy");
   if (time_out) *time_out = d->t;
@@ -398,7 +400,8 @@ int nplbm_set_state(nplbm_domain *d, const void *host, int64_t time) {
   if (e == hipSuccess)
     e = hipMemcpyAsync(d->base + d->L.g[par], o + hb, gb, hipMemcpyHostToDevice, d->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(d->base + d->L.prev, o + hb + gb, pb, hipMemcpyHostToDevice, d->stream);
+    e = hipMemcpyAsync(d->base + d->L.prev[par], o + hb + gb, pb, hipMemcpyHostToDevice,
+                       d->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(d->stream);
   if (e != hipSuccess) return hip_fail(e, "state copy");
   d->t = time;

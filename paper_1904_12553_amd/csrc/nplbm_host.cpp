@@ -310,7 +310,7 @@ Layout plan_layout(const nplbm_params *p) {
   };
   for (int b = 0; b < 2; ++b) L.h[b] = take((size_t)M * 9 * L.plane * s);
   for (int b = 0; b < 2; ++b) L.g[b] = take((size_t)8 * L.plane * s);
-  L.prev = take((size_t)(M + 2) * L.plane * s);
+  for (int b = 0; b < 2; ++b) L.prev[b] = take((size_t)(M + 2) * L.plane * s);
   L.state_end = off;
   L.desc = take(sizeof(DomDesc));
   L.nstrips = 0;

@@ -44,9 +44,10 @@ struct Consts {
 
 // One resident domain as the kernels see it.
 struct DomDesc {
-  void *h[2];        // CH populations, [(N-1)][9][ny][pitch], ping-pong
+  void *h[2];        // CH populations, [(N-1)][9][ny][pitch], ping-pong; the
+                     // k = 0 plane holds h_0 - phi_prev (see below)
   void *g[2];        // NS populations k = 1..8, [8][ny][pitch], ping-pong
-  void *prev;        // previous phi_i (N-1 planes) and u (2 planes), in place
+  void *prev[2];     // previous-step phi_i (N-1 planes) and u (2 planes), ping-pong
   int64_t plane;     // elements per plane = ny * pitch
   int32_t nx, ny, pitch, wall;
   int32_t N;

@@ -116,7 +116,8 @@ int admit(nplbm_server *s, Req *r) {
     D.h[b] = r->base + r->L.h[b];
     D.g[b] = r->base + r->L.g[b];
   }
-  D.prev = r->base + r->L.prev;
+  D.prev[0] = r->base + r->L.prev[0];
+  D.prev[1] = r->base + r->L.prev[1];
   D.plane = r->L.plane;
   D.nx = r->p.nx;
   D.ny = r->p.ny;

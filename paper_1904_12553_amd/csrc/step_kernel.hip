@@ -21,11 +21,19 @@
 //
 // So every population is read from HBM once and written once per step; the
 // only re-reads are the 2-column x-halo and a 4-row ramp at the strip start,
-// both L2/MALL-resident.  Rest populations are dropped or derived:
+// both L2/MALL-resident.  Rest populations are dropped or stored as
+// deviations from their rest-state value:
 //   - g_0 never feeds u, p or phi (c_0 = 0 and eq:N23 sums k != 0), so only
-//     g_1..g_8 are stored;
-//   - h_0 after collision is phi_i - sum_{k>=1} h_k (the collision conserves
-//     sum_k h_k = phi_i exactly), so a uniform bulk node is stationary.
+//     g_1..g_8 are stored; at rest (p = 0, u = 0) their equilibria are 0, so
+//     they are already deviations;
+//   - the rest population h_0 carries the O(1) order parameter.  The
+//     collision conserves sum_k h_k = phi_i, so the stored k = 0 value is the
+//     deviation d_i = h_0 - phi_i(prev) of h_0 from the rest value phi_i,
+//     with phi_i(prev) the rounded phi_i the same node stores for the source
+//     term (eq:N27).  phi_i is then carried as an unevaluated sum
+//     hi + lo = phi_prev + (d + sum_{k>=1} h_k) and never rounded to one
+//     storage word, so in FP32 the state keeps ~1e-11 absolute resolution on
+//     phi instead of ~6e-8.
 //
 // Boundaries: x periodic; y periodic or halfway bounce-back walls (a
 // population that would be pulled from outside is the node's own opposite
@@ -59,7 +67,8 @@ __global__ void __launch_bounds__(kStepThreads) k_step(StepArgs a) {
   Real *__restrict__ hd = static_cast<Real *>(D->h[par ^ 1]);
   const Real *__restrict__ gs = static_cast<const Real *>(D->g[par]);
   Real *__restrict__ gd = static_cast<Real *>(D->g[par ^ 1]);
-  Real *__restrict__ pv = static_cast<Real *>(D->prev);
+  const Real *__restrict__ pvs = static_cast<const Real *>(D->prev[par]);
+  Real *__restrict__ pvd = static_cast<Real *>(D->prev[par ^ 1]);
   const Consts<Real> &K = consts_of<Real>(D);
   const int nx = D->nx, ny = D->ny, pitch = D->pitch;
   const bool wall = D->wall != 0;
@@ -121,8 +130,16 @@ __global__ void __launch_bounds__(kStepThreads) k_step(StepArgs a) {
     return ro + co;
   };
 
+  // lo part of phi_i: the stored deviation of h_0 plus the moving populations
+  auto lo_sum = [&](const Real (&h)[9]) {
+    Real lo = h[0];
+#pragma unroll
+    for (int k = 1; k < 9; ++k) lo += h[k];
+    return lo;
+  };
+
   // ---- stage A: pull CH populations for march index mA, phi -> LDS ----
-  auto stageA = [&](int mA, Real (&cur)[M][9]) {
+  auto stageA = [&](int mA, Real (&cur)[M][9], Real (&hi)[M]) {
     const int yp = phys_row(row_of(mA));
     const Src s = make_src(yp);
 #pragma unroll
@@ -132,14 +149,11 @@ __global__ void __launch_bounds__(kStepThreads) k_step(StepArgs a) {
 #pragma unroll
       for (int i = 0; i < M; ++i) cur[i][k] = hs[(int64_t)(i * 9 + kk) * plane + off];
     }
+#pragma unroll
+    for (int i = 0; i < M; ++i) hi[i] = pvs[(int64_t)i * plane + s.o0 + xc];
     const int slot = (mA + 8) & 7;
 #pragma unroll
-    for (int i = 0; i < M; ++i) {
-      Real ph = cur[i][0];
-#pragma unroll
-      for (int k = 1; k < 9; ++k) ph += cur[i][k];
-      sphi[slot][i][lane] = ph;
-    }
+    for (int i = 0; i < M; ++i) sphi[slot][i][lane] = hi[i] + lo_sum(cur[i]);  // eq:N28
   };
 
   // ---- stage B: chemical potentials for march index mB -> LDS ----
@@ -186,7 +200,7 @@ __global__ void __launch_bounds__(kStepThreads) k_step(StepArgs a) {
   };
 
   // ---- stage C: collide march index mC with the populations in hh ----
-  auto stageC = [&](int mC, Real (&hh)[M][9]) {
+  auto stageC = [&](int mC, Real (&hh)[M][9], const Real (&hhi)[M]) {
     if (!interior || mC < 0 || mC >= H) return;
     const int yp = row_of(mC);
     const int p0 = (mC + 8) & 7, pN = (mC + dir + 8) & 7, pS = (mC - dir + 8) & 7;
@@ -287,11 +301,11 @@ __global__ void __launch_bounds__(kStepThreads) k_step(StepArgs a) {
       gd[(int64_t)(k - 1) * plane + orow] = g[k] - itau * (g[k] - geq) + srcg * G;
     }
     // CH collisions
-    const Real pux = pv[(int64_t)M * plane + orow];
-    const Real puy = pv[(int64_t)(M + 1) * plane + orow];
+    const Real pux = pvs[(int64_t)M * plane + orow];
+    const Real puy = pvs[(int64_t)(M + 1) * plane + orow];
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-      const Real pp = pv[(int64_t)i * plane + orow];
+      const Real pp = hhi[i];  // phi_i of the previous step (stored)
       const Real psx = phi[i] * ux, psy = phi[i] * uy;
       const Real dx = psx - pp * pux, dy = psy - pp * puy;  // eq:N27
       const Real ec = K.eta_i[i] * Cv[i];
@@ -307,31 +321,37 @@ __global__ void __launch_bounds__(kStepThreads) k_step(StepArgs a) {
         hsum += hn;
         hd[(int64_t)(i * 9 + k) * plane + orow] = hn;
       }
-      hd[(int64_t)(i * 9) * plane + orow] = phi[i] - hsum;
-      pv[(int64_t)i * plane + orow] = phi[i];
+      // phi_i = hi + lo exactly; phi[i] = fl(hi + lo) is stored as the new
+      // previous phi and the k = 0 slot keeps (hi + lo - phi[i]) - sum h_k
+      // (error-free two-sum for the rounding part).
+      const Real lo = lo_sum(hh[i]);
+      const Real bb = phi[i] - pp;
+      const Real err = (pp - (phi[i] - bb)) + (lo - bb);
+      hd[(int64_t)(i * 9) * plane + orow] = err - hsum;
+      pvd[(int64_t)i * plane + orow] = phi[i];
     }
-    pv[(int64_t)M * plane + orow] = ux;
-    pv[(int64_t)(M + 1) * plane + orow] = uy;
+    pvd[(int64_t)M * plane + orow] = ux;
+    pvd[(int64_t)(M + 1) * plane + orow] = uy;
   };
 
-  Real bufA[M][9], bufB[M][9];
+  Real bufA[M][9], bufB[M][9], hiA[M], hiB[M];
   const int J = (H + 5) / 2;
   for (int j = 0; j < J; j += 2) {
     {
       const int mA = 2 * j - 2 + ry;
-      stageA(mA, bufA);
+      stageA(mA, bufA, hiA);
       __syncthreads();
       stageB(mA - 1);
       __syncthreads();
-      stageC(mA - 2, bufB);
+      stageC(mA - 2, bufB, hiB);
     }
     {
       const int mA = 2 * (j + 1) - 2 + ry;
-      stageA(mA, bufB);
+      stageA(mA, bufB, hiB);
       __syncthreads();
       stageB(mA - 1);
       __syncthreads();
-      stageC(mA - 2, bufA);
+      stageC(mA - 2, bufA, hiA);
     }
   }
 }

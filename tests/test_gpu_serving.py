@@ -1,0 +1,69 @@
+"""Serving: continuous batching of mixed-N, mixed-size domains gives the
+same result for every request as running it alone (bitwise, FP32), with
+requests admitted while others are resident and finishing mid-quantum."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _alone(w, steps):
+    import paper_1904_12553_amd as P
+    d = P.Domain(precision=32, **w.params())
+    d.set_fields(w.c, w.u)
+    d.step(steps)
+    return d.macro()
+
+
+def test_alone_equals_mix():
+    import paper_1904_12553_amd as P
+    reqs = [W.Request(i, 0.0, N, side, steps, W.BASE_SEED * 10 + i)
+            for i, (N, side, steps) in enumerate([(3, 64, 37), (4, 96, 120), (5, 128, 75),
+                                                   (3, 80, 200), (5, 64, 13), (4, 64, 90)])]
+    ws = [W.request_workload(r, accept=P.accepts) for r in reqs]
+    srv = P.Server(hbm_budget=1 << 30, max_slots=4, quantum=16)
+    tickets = []
+    # first three now, the rest after two quanta (admitted into a running mix)
+    for r, w in list(zip(reqs, ws))[:3]:
+        tickets.append(srv.submit(w.c, w.u, nsteps=r.steps, precision=32, **w.params()))
+    srv.pump()
+    srv.pump()
+    for r, w in list(zip(reqs, ws))[3:]:
+        tickets.append(srv.submit(w.c, w.u, nsteps=r.steps, precision=32, **w.params()))
+    results = {}
+    for _ in range(1000):
+        srv.pump()
+        for t in tickets:
+            if t not in results and srv.poll(t) == 2:
+                results[t] = srv.result(t)
+        if len(results) == len(tickets):
+            break
+    assert len(results) == len(tickets)
+    for t, r, w in zip(tickets, reqs, ws):
+        c, u, p, adm, fin = results[t]
+        ca, ua, pa = _alone(w, r.steps)
+        assert np.array_equal(c, ca) and np.array_equal(u, ua) and np.array_equal(p, pa), r
+        assert fin >= adm >= 0.0
+    nu, busy, done = srv.stats()
+    assert done == len(reqs)
+    assert nu == pytest.approx(sum(w.nx * w.ny * r.steps for r, w in zip(reqs, ws)))
+
+
+def test_budget_admission_and_too_big():
+    import paper_1904_12553_amd as P
+    w = W.static_droplet(64, 64, R=16, precision=32)
+    fp = P.footprint(precision=32, **w.params())
+    srv = P.Server(hbm_budget=int(fp * 1.5), max_slots=8, quantum=10)
+    t1 = srv.submit(w.c, None, nsteps=30, precision=32, **w.params())
+    t2 = srv.submit(w.c, None, nsteps=30, precision=32, **w.params())
+    srv.pump()
+    assert srv.poll(t1) == 1 and srv.poll(t2) == 0   # only one fits the budget
+    big = W.static_droplet(128, 128, R=30, precision=32)
+    with pytest.raises(P.NplbmError) as e:
+        srv.submit(big.c, None, nsteps=10, precision=32, **big.params())
+    assert e.value.code == -5
+    for _ in range(20):
+        srv.pump()
+    assert srv.poll(t1) == 2 and srv.poll(t2) == 2
