@@ -30,6 +30,11 @@ __device__ __forceinline__ int64_t nb(int x, int y, int dx, int dy, int nx, int 
   return (int64_t)yy * nx + xx;
 }
 
+// Element offset of (plane p, row y, column x) in state group G.
+__device__ __forceinline__ int64_t at(const DomDesc *dd, int G, int p, int y, int x) {
+  return (int64_t)p * dd->ps[G] + (int64_t)y * dd->rs[G] + x;
+}
+
 // eq:N31b on a dense (ny x nx) double plane
 __device__ __forceinline__ double lap9(const double *f, int x, int y, int nx, int ny, bool wall) {
   const double c = f[(int64_t)y * nx + x];
@@ -110,7 +115,6 @@ __global__ void k_init_dist(const DomDesc *dd, int M, const double *phi, const d
   const int x = (int)(id % nx), y = (int)(id / nx);
   const bool wall = dd->wall != 0;
   const Consts<double> &K = dd->cd;
-  const int64_t plane = dd->plane;
   Real *h = static_cast<Real *>(dd->h[dd->parity0]);
   Real *g = static_cast<Real *>(dd->g[dd->parity0]);
   Real *pv = static_cast<Real *>(dd->prev[dd->parity0]);
@@ -118,17 +122,16 @@ __global__ void k_init_dist(const DomDesc *dd, int M, const double *phi, const d
   double rho = K.ra;
   for (int i = 0; i < M; ++i) rho += K.rA[i] * phi[(int64_t)i * n + id];
   const double usq = ux * ux + uy * uy;
-  const int64_t self = (int64_t)y * pitch + x;
   for (int k = 0; k < 9; ++k) {
     const int cx = cxk(k), cy = cyk(k);
-    const int ys = y - cy;
-    int64_t off;
+    int ys = y - cy, xs = wrapi(x - cx, nx);
     int kk = k;
     if (wall && (ys < 0 || ys >= ny)) {
       kk = oppk(k);
-      off = self;
+      ys = y;
+      xs = x;
     } else {
-      off = (int64_t)wrapi(ys, ny) * pitch + wrapi(x - cx, nx);
+      ys = wrapi(ys, ny);
     }
     const double w = wk<double>(k);
     const double cu = cx * ux + cy * uy;
@@ -138,16 +141,16 @@ __global__ void k_init_dist(const DomDesc *dd, int M, const double *phi, const d
       // k = 0: h_0^eq - phi_stored with phi_stored = (Real)phi
       const double v = (k == 0) ? (ph - (double)(Real)ph) + (w - 1.0) * ec
                                 : w * ec + w * 3.0 * (cx * ph * ux + cy * ph * uy);
-      h[(int64_t)(i * 9 + kk) * plane + off] = (Real)v;
+      h[at(dd, 0, i * 9 + kk, ys, xs)] = (Real)v;
     }
     if (k > 0) {
       const double v = rho * w * (3.0 * cu + 4.5 * cu * cu - 1.5 * usq);  // p = 0
-      g[(int64_t)(kk - 1) * plane + off] = (Real)v;
+      g[at(dd, 1, kk - 1, ys, xs)] = (Real)v;
     }
   }
-  for (int i = 0; i < M; ++i) pv[(int64_t)i * plane + self] = (Real)phi[(int64_t)i * n + id];
-  pv[(int64_t)M * plane + self] = (Real)ux;
-  pv[(int64_t)(M + 1) * plane + self] = (Real)uy;
+  for (int i = 0; i < M; ++i) pv[at(dd, 2, i, y, x)] = (Real)phi[(int64_t)i * n + id];
+  pv[at(dd, 2, M, y, x)] = (Real)ux;
+  pv[at(dd, 2, M + 1, y, x)] = (Real)uy;
 }
 
 // --------------------------------------------------------------- macro ----
@@ -161,26 +164,25 @@ __global__ void k_macro_phi(const DomDesc *dd, int M, int parity, double *phi, d
   if (id >= n) return;
   const int x = (int)(id % nx), y = (int)(id / nx);
   const bool wall = dd->wall != 0;
-  const int64_t plane = dd->plane;
   const Real *h = static_cast<const Real *>(dd->h[parity]);
   const Real *pv = static_cast<const Real *>(dd->prev[parity]);
   const Consts<double> &K = dd->cd;
   const int N = M + 1;
   double ph[kMaxM];
   // phi_i = phi_prev + (h_0 - phi_prev) + sum_{k>=1} h_k (eq:N28)
-  for (int i = 0; i < M; ++i) ph[i] = (double)pv[(int64_t)i * plane + (int64_t)y * pitch + x];
+  for (int i = 0; i < M; ++i) ph[i] = (double)pv[at(dd, 2, i, y, x)];
   for (int k = 0; k < 9; ++k) {
     const int cx = cxk(k), cy = cyk(k);
-    const int ys = y - cy;
-    int64_t off;
+    int ys = y - cy, xs = wrapi(x - cx, nx);
     int kk = k;
     if (wall && (ys < 0 || ys >= ny)) {
       kk = oppk(k);
-      off = (int64_t)y * pitch + x;
+      ys = y;
+      xs = x;
     } else {
-      off = (int64_t)wrapi(ys, ny) * pitch + wrapi(x - cx, nx);
+      ys = wrapi(ys, ny);
     }
-    for (int i = 0; i < M; ++i) ph[i] += (double)h[(int64_t)(i * 9 + kk) * plane + off];
+    for (int i = 0; i < M; ++i) ph[i] += (double)h[at(dd, 0, i * 9 + kk, ys, xs)];
   }
   double r = K.ra;
   for (int i = 0; i < M; ++i) {
@@ -206,7 +208,6 @@ __global__ void k_macro_up(const DomDesc *dd, int M, int parity, const double *p
   if (id >= n) return;
   const int x = (int)(id % nx), y = (int)(id / nx);
   const bool wall = dd->wall != 0;
-  const int64_t plane = dd->plane;
   const Real *g = static_cast<const Real *>(dd->g[parity]);
   const Consts<double> &K = dd->cd;
   double Fx = 0.0, Fy = 0.0, grx = 0.0, gry = 0.0;
@@ -226,16 +227,16 @@ __global__ void k_macro_up(const DomDesc *dd, int M, int parity, const double *p
   gk[0] = 0.0;
   for (int k = 1; k < 9; ++k) {
     const int cx = cxk(k), cy = cyk(k);
-    const int ys = y - cy;
-    int64_t off;
+    int ys = y - cy, xs = wrapi(x - cx, nx);
     int kk = k;
     if (wall && (ys < 0 || ys >= ny)) {
       kk = oppk(k);
-      off = (int64_t)y * pitch + x;
+      ys = y;
+      xs = x;
     } else {
-      off = (int64_t)wrapi(ys, ny) * pitch + wrapi(x - cx, nx);
+      ys = wrapi(ys, ny);
     }
-    gk[k] = (double)g[(int64_t)(kk - 1) * plane + off];
+    gk[k] = (double)g[at(dd, 1, kk - 1, ys, xs)];
   }
   double mx = 0.0, my = 0.0, sg = 0.0;
   for (int k = 1; k < 9; ++k) {

@@ -29,7 +29,8 @@ int derive(const nplbm_params *p, Derived &d);
 // Byte offsets of every device buffer of one domain inside its allocation.
 struct Layout {
   int pitch = 0;
-  int64_t plane = 0;
+  int64_t ps[3] = {0, 0, 0}, rs[3] = {0, 0, 0};  // element strides (see DomDesc)
+  size_t gbytes[3] = {0, 0, 0};                  // bytes of one copy of each group
   size_t h[2] = {0, 0}, g[2] = {0, 0}, prev[2] = {0, 0}, state_end = 0;
   size_t desc = 0, strips = 0;
   int nstrips = 0;
@@ -39,8 +40,17 @@ struct Layout {
   size_t total = 0;
 };
 Layout plan_layout(const nplbm_params *p);
+int single_domain_target(const nplbm_params *p);
 
-void build_strips(int nx, int ny, int dom, std::vector<StripDesc> &out, int target = 0);
+// default padding of every population plane (64 elements of 4 bytes)
+constexpr size_t kPlanePadBytes = 256;
+int64_t plane_pad(size_t elem);
+// default padding of every row block of the row-interleaved layout
+constexpr size_t kRowPadBytes = 0;
+int64_t row_pad(size_t elem);
+int resident_step_blocks(int N, int precision);
+void build_strips(int nx, int ny, int dom, const StepGeom &geom, std::vector<StripDesc> &out,
+                  int target = 0);
 void xcd_order(std::vector<StripDesc> &s);
 
 }  // namespace nplbm

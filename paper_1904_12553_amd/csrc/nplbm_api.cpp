@@ -27,6 +27,7 @@ struct nplbm_domain {
   DomDesc *desc_dev = nullptr;
   StripDesc *strips_dev = nullptr;
   int nstrips = 0;
+  StepGeom geom{64, 60, 1};  // strip geometry of the step kernel
   int64_t t = 0;
   bool initialised = false;
   // graph of kGraphSteps consecutive steps starting from an even time
@@ -46,7 +47,7 @@ int launch_one_step(nplbm_domain *d) {
   a.strips = d->strips_dev;
   a.doms = d->desc_dev;
   a.substep = (int)(d->t & 1);
-  hipError_t e = launch_step(d->p.N, d->p.precision, a, d->nstrips, d->stream);
+  hipError_t e = launch_step(d->p.N, d->p.precision, d->geom.bw, a, d->nstrips, d->stream);
   if (e != hipSuccess) return hip_fail(e, "step launch");
   d->t += 1;
   return NPLBM_OK;
@@ -65,7 +66,7 @@ int capture_graph(nplbm_domain *d) {
   hipError_t le = hipSuccess;
   for (int s = 0; s < kGraphSteps && le == hipSuccess; ++s) {
     a.substep = s & 1;
-    le = launch_step(d->p.N, d->p.precision, a, d->nstrips, d->stream);
+    le = launch_step(d->p.N, d->p.precision, d->geom.bw, a, d->nstrips, d->stream);
   }
   e = hipStreamEndCapture(d->stream, &g);
   if (le != hipSuccess) {
@@ -189,7 +190,10 @@ int nplbm_create(const nplbm_params *p, void *stream, void *device_mem, size_t d
   }
   D.prev[0] = d->base + d->L.prev[0];
   D.prev[1] = d->base + d->L.prev[1];
-  D.plane = d->L.plane;
+  for (int G = 0; G < 3; ++G) {
+    D.ps[G] = d->L.ps[G];
+    D.rs[G] = d->L.rs[G];
+  }
   D.nx = p->nx;
   D.ny = p->ny;
   D.pitch = d->L.pitch;
@@ -201,8 +205,13 @@ int nplbm_create(const nplbm_params *p, void *stream, void *device_mem, size_t d
   D.cf = d->d.cf;
   d->desc_dev = reinterpret_cast<DomDesc *>(d->base + d->L.desc);
   std::vector<StripDesc> strips;
-  build_strips(p->nx, p->ny, 0, strips);
+  d->geom = step_geom(p->N, p->precision);
+  build_strips(p->nx, p->ny, 0, d->geom, strips, single_domain_target(p));
   xcd_order(strips);
+  if ((int)strips.size() > d->L.nstrips) {
+    nplbm_destroy(d);
+    return fail(NPLBM_EINVAL, "strip table overflow");
+  }
   d->nstrips = (int)strips.size();
   d->strips_dev = reinterpret_cast<StripDesc *>(d->base + d->L.strips);
   e = hipMemcpyAsync(d->desc_dev, &D, sizeof D, hipMemcpyHostToDevice, d->stream);
@@ -363,7 +372,9 @@ size_t nplbm_state_bytes(const nplbm_domain *d) {
   if (!d) return 0;
   const size_t s = d->p.precision == 64 ? 8 : 4;
   const int M = d->p.N - 1;
-  return ((size_t)M * 9 + 8 + (size_t)M + 2) * (size_t)d->L.plane * s;
+  (void)s;
+  (void)M;
+  return d->L.gbytes[0] + d->L.gbytes[1] + d->L.gbytes[2];
 }
 
 int nplbm_get_state(nplbm_domain *d, void *host, int64_t *time_out) {
@@ -372,8 +383,9 @@ int nplbm_get_state(nplbm_domain *d, void *host, int64_t *time_out) {
   const size_t s = d->p.precision == 64 ? 8 : 4;
   const int M = d->p.N - 1;
   const int par = (int)(d->t & 1);
-  const size_t hb = (size_t)M * 9 * d->L.plane * s, gb = (size_t)8 * d->L.plane * s,
-               pb = (size_t)(M + 2) * d->L.plane * s;
+  const size_t hb = d->L.gbytes[0], gb = d->L.gbytes[1], pb = d->L.gbytes[2];
+  (void)s;
+  (void)M;
   unsigned char *o = static_cast<unsigned char *>(host);
   hipError_t e = hipMemcpyAsync(o, d->base + d->L.h[par], hb, hipMemcpyDeviceToHost, d->stream);
   if (e == hipSuccess)
@@ -393,8 +405,9 @@ int nplbm_set_state(nplbm_domain *d, const void *host, int64_t time) {
   const size_t s = d->p.precision == 64 ? 8 : 4;
   const int M = d->p.N - 1;
   const int par = (int)(time & 1);
-  const size_t hb = (size_t)M * 9 * d->L.plane * s, gb = (size_t)8 * d->L.plane * s,
-               pb = (size_t)(M + 2) * d->L.plane * s;
+  const size_t hb = d->L.gbytes[0], gb = d->L.gbytes[1], pb = d->L.gbytes[2];
+  (void)s;
+  (void)M;
   const unsigned char *o = static_cast<const unsigned char *>(host);
   hipError_t e = hipMemcpyAsync(d->base + d->L.h[par], o, hb, hipMemcpyHostToDevice, d->stream);
   if (e == hipSuccess)

@@ -295,31 +295,80 @@ int derive(const nplbm_params *p, Derived &d) {
 // ------------------------------------------------------------ memory plan
 static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// Padding (in elements) appended to every population plane.  Without it the
+// ~10N planes a node touches are a power of two apart for power-of-two
+// lattices and fall onto the same HBM channels.
+int64_t plane_pad(size_t elem) {
+  if (const char *e = std::getenv("NPLBM_PLANE_PAD")) return std::atoll(e);
+  return (int64_t)(kPlanePadBytes / elem);
+}
+
+// Padding (in elements) appended to every row block of the row-interleaved
+// layout.
+int64_t row_pad(size_t elem) {
+  if (const char *e = std::getenv("NPLBM_ROW_PAD")) return std::atoll(e);
+  return (int64_t)(kRowPadBytes / elem);
+}
+
+// Workgroups the step kernel can keep resident on the device at once.
+int resident_step_blocks(int N, int precision) {
+  static int cus = -1;
+  if (cus < 0) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      cus = prop.multiProcessorCount;
+    else
+      cus = 0;
+  }
+  const int per = step_blocks_per_cu(N, precision, step_geom(N, precision).bw);
+  return cus > 0 && per > 0 ? cus * per : 0;
+}
+
+// Strip count for a single-domain launch: one full round of resident
+// workgroups (no tail), unless overridden.
+int single_domain_target(const nplbm_params *p) {
+  if (const char *env = std::getenv("NPLBM_TARGET_BLOCKS")) {
+    const int t = std::atoi(env);
+    if (t > 0) return t;
+  }
+  const int r = resident_step_blocks(p->N, p->precision);
+  return r > 0 ? r : 2048;
+}
+
 Layout plan_layout(const nplbm_params *p) {
   Layout L;
   const int N = p->N, M = N - 1;
   const size_t s = p->precision == 64 ? 8 : 4;
   L.pitch = (p->nx + 15) & ~15;
-  L.plane = (int64_t)L.pitch * p->ny;
   const size_t n = (size_t)p->nx * p->ny;
+  const int np[3] = {M * 9, 8, M + 2};  // planes per group
+  const char *lay = std::getenv("NPLBM_LAYOUT");
+  const bool soa = lay && std::strcmp(lay, "soa") == 0;
+  for (int G = 0; G < 3; ++G) {
+    if (soa) {
+      L.ps[G] = (int64_t)L.pitch * p->ny + plane_pad(s);
+      L.rs[G] = L.pitch;
+      L.gbytes[G] = (size_t)np[G] * L.ps[G] * s;
+    } else {
+      L.ps[G] = L.pitch;
+      L.rs[G] = (int64_t)np[G] * L.pitch + row_pad(s);
+      L.gbytes[G] = (size_t)p->ny * L.rs[G] * s;
+    }
+  }
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
     off += al256(bytes);
     return o;
   };
-  for (int b = 0; b < 2; ++b) L.h[b] = take((size_t)M * 9 * L.plane * s);
-  for (int b = 0; b < 2; ++b) L.g[b] = take((size_t)8 * L.plane * s);
-  for (int b = 0; b < 2; ++b) L.prev[b] = take((size_t)(M + 2) * L.plane * s);
+  for (int b = 0; b < 2; ++b) L.h[b] = take(L.gbytes[0]);
+  for (int b = 0; b < 2; ++b) L.g[b] = take(L.gbytes[1]);
+  for (int b = 0; b < 2; ++b) L.prev[b] = take(L.gbytes[2]);
   L.state_end = off;
   L.desc = take(sizeof(DomDesc));
-  L.nstrips = 0;
-  {
-    std::vector<StripDesc> tmp;
-    build_strips(p->nx, p->ny, 0, tmp);
-    xcd_order(tmp);
-    L.nstrips = (int)tmp.size();
-  }
+  // room for any strip decomposition (strip height >= 2, XCD padding)
+  L.nstrips = ((p->nx + 7) / 8) * ((p->ny + 1) / 2) + 8;
   L.strips = take(sizeof(StripDesc) * (size_t)L.nstrips);
   L.phi = take((size_t)M * n * 8);
   L.rho = take(n * 8);
@@ -334,19 +383,53 @@ Layout plan_layout(const nplbm_params *p) {
   return L;
 }
 
+// Strip geometry of the step kernel for a precision.  Interior strip widths
+// are multiples of 64 bytes of state, so no 64-byte memory sector is written
+// by two workgroups.
+// Interior widths are multiples of one 128-byte cache line of state values
+// (32 floats or 16 doubles), so no line is written by two workgroups; rows
+// of 256 threads for FP32 and 64 for FP64 measured fastest on gfx950.
+StepGeom step_geom(int N, int precision) {
+  StepGeom g;
+  const int unit = precision == 64 ? 16 : 32;
+  g.bw = precision == 64 ? 64 : 256;
+  if (const char *e = std::getenv("NPLBM_BW")) {
+    const int b = std::atoi(e);
+    g.bw = (b == 128 || b == 256) ? b : 64;
+  }
+  g.bw = std::min(g.bw, step_max_bw(N, precision));
+  g.tx = ((g.bw - 4) / unit) * unit;
+  if (const char *e = std::getenv("NPLBM_TX")) g.tx = std::atoi(e);
+  if (g.tx < 8) g.tx = 8;
+  if (g.tx > g.bw - 4) g.tx = g.bw - 4;
+  g.unit = unit;
+  return g;
+}
+
 // Strip decomposition of one domain for the marching step kernel.  Strips
-// are kTX interior columns wide and H rows tall, H chosen so that the whole
+// are geom.tx interior columns wide and H rows tall, H chosen so that the whole
 // launch has about `target` workgroups; neighbouring strip rows march in
 // opposite directions, so the halo rows they share are read at the same
 // time (both at their start or both at their end).
-void build_strips(int nx, int ny, int dom, std::vector<StripDesc> &out, int target) {
+void build_strips(int nx, int ny, int dom, const StepGeom &geom, std::vector<StripDesc> &out,
+                  int target) {
+  const int kTX = geom.tx;
+  const int unit = std::max(1, std::min(geom.unit, kTX));
   if (target <= 0) {
     const char *env = std::getenv("NPLBM_TARGET_BLOCKS");
     target = env ? std::atoi(env) : 2048;
     if (target <= 0) target = 2048;
   }
-  const int nsx = (nx + kTX - 1) / kTX;
-  int nsy = (target + nsx - 1) / nsx;
+  // strips in x: widths in whole cache-line units, as equal as possible
+  const int units = (nx + unit - 1) / unit;
+  const int per_max = std::max(1, kTX / unit);
+  const int nsx = (units + per_max - 1) / per_max;
+  std::vector<int> xs(nsx + 1, 0);
+  for (int sx = 0; sx < nsx; ++sx) {
+    const int u = units / nsx + (sx < units % nsx ? 1 : 0);
+    xs[sx + 1] = std::min(nx, xs[sx] + u * unit);
+  }
+  int nsy = std::max(1, target / nsx);
   int H = (ny + nsy - 1) / std::max(nsy, 1);
   int hmin = 16;
   if (const char *e = std::getenv("NPLBM_MIN_STRIP_H")) hmin = std::max(2, std::atoi(e));
@@ -358,7 +441,8 @@ void build_strips(int nx, int ny, int dom, std::vector<StripDesc> &out, int targ
       StripDesc s;
       std::memset(&s, 0, sizeof s);
       s.dom = dom;
-      s.x0 = sx * kTX;
+      s.x0 = xs[sx];
+      s.x1 = xs[sx + 1];
       s.y0 = sy * H;
       s.y1 = std::min(ny, (sy + 1) * H);
       s.dir = (sy & 1) ? -1 : 1;

@@ -9,10 +9,20 @@ namespace nplbm {
 
 constexpr int kMaxN = 8;          // phases
 constexpr int kMaxM = kMaxN - 1;  // order parameters
-constexpr int kBW = 64;           // lanes per strip row (one wave)
-constexpr int kTX = kBW - 4;      // interior columns per strip (2-column halo each side)
-constexpr int kRows = 2;          // rows per marching iteration (one wave per row)
-constexpr int kStepThreads = kBW * kRows;
+constexpr int kRows = 2;  // rows per marching iteration (one or more waves per row)
+// Row width of a step workgroup in threads (a multiple of the 64-lane wave):
+// each row covers the strip's interior columns plus a 2-column halo on each
+// side; lanes beyond that stay idle.
+struct StepGeom {
+  int bw;    // threads per row (64, 128 or 256)
+  int tx;    // maximum interior columns per strip (<= bw - 4)
+  int unit;  // strip widths are multiples of this many columns (one cache line)
+};
+// Geometry used for N phases at a precision (32 / 64); NPLBM_BW and
+// NPLBM_TX override.
+StepGeom step_geom(int N, int precision);
+// widest row width the step kernel is built with for (N, precision)
+int step_max_bw(int N, int precision);
 
 // Per-domain constants, folded on the host from the paper's closure so that
 // every per-node quantity is an affine map or a short dot product:
@@ -48,7 +58,11 @@ struct DomDesc {
                      // k = 0 plane holds h_0 - phi_prev (see below)
   void *g[2];        // NS populations k = 1..8, [8][ny][pitch], ping-pong
   void *prev[2];     // previous-step phi_i (N-1 planes) and u (2 planes), ping-pong
-  int64_t plane;     // elements per plane = ny * pitch
+  // Element (plane p, row y, column x) of group G (0: h, 1: g, 2: prev) is at
+  // base + p * ps[G] + y * rs[G] + x.  The default layout interleaves planes
+  // by row (ps = row pitch, rs = planes x pitch), so the populations one row
+  // of nodes needs are one contiguous block.
+  int64_t ps[3], rs[3];
   int32_t nx, ny, pitch, wall;
   int32_t N;
   int32_t parity0;   // buffer holding the current state at substep 0
@@ -65,7 +79,8 @@ struct StripDesc {
   int32_t dom;
   int32_t x0, y0, y1;
   int32_t dir;
-  int32_t pad_[3];
+  int32_t x1;  // end of the interior columns (exclusive, <= nx)
+  int32_t pad_[2];
 };
 
 struct StepArgs {
@@ -76,7 +91,10 @@ struct StepArgs {
 };
 
 // Launchers (defined in the .hip files).  All are asynchronous on `st`.
-hipError_t launch_step(int N, int precision, const StepArgs &a, int nblocks, hipStream_t st);
+hipError_t launch_step(int N, int precision, int bw, const StepArgs &a, int nblocks,
+                       hipStream_t st);
+// resident step-kernel workgroups per compute unit (0 if unknown)
+int step_blocks_per_cu(int N, int precision, int bw);
 
 // Initialisation: phi (double, (N-1) planes of nx*ny) is computed from c,
 // then C from phi, then h^eq / g^eq written in pull layout.

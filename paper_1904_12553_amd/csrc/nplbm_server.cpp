@@ -118,7 +118,10 @@ int admit(nplbm_server *s, Req *r) {
   }
   D.prev[0] = r->base + r->L.prev[0];
   D.prev[1] = r->base + r->L.prev[1];
-  D.plane = r->L.plane;
+  for (int G = 0; G < 3; ++G) {
+    D.ps[G] = r->L.ps[G];
+    D.rs[G] = r->L.rs[G];
+  }
   D.nx = r->p.nx;
   D.ny = r->p.ny;
   D.pitch = r->L.pitch;
@@ -170,7 +173,7 @@ int rebuild(nplbm_server *s) {
       for (int slot = 0; slot < s->max_slots; ++slot) {
         Req *r = s->slots[slot];
         if (!r || r->p.N != N || r->p.precision != prec) continue;
-        build_strips(r->p.nx, r->p.ny, slot, g);
+        build_strips(r->p.nx, r->p.ny, slot, step_geom(N, prec), g);
       }
       if (g.empty()) continue;
       xcd_order(g);
@@ -204,7 +207,8 @@ int rebuild(nplbm_server *s) {
       a.strips = s->strips_dev + gr.off;
       a.doms = s->descs_dev;
       a.substep = q;
-      le = launch_step(gr.N, gr.precision, a, (int)gr.count, s->stream);
+      le = launch_step(gr.N, gr.precision, step_geom(gr.N, gr.precision).bw, a,
+                       (int)gr.count, s->stream);
       if (le != hipSuccess) break;
     }
   e = hipStreamEndCapture(s->stream, &g);

@@ -44,48 +44,106 @@
 
 namespace nplbm {
 
+// Address spaces: the descriptors and constants are read-only for the whole
+// launch and uniform per workgroup, so they are read through constant
+// (scalar-load) pointers; the state arrays are global-memory pointers so the
+// loads are global (not flat) loads with a per-plane scalar base and one
+// shared 32-bit lane offset.
+#define NPL_GLOBAL __attribute__((address_space(1)))
+#define NPL_CONST __attribute__((address_space(4)))
+
+// Element access by 32-bit byte offset from a (scalar) plane base, so that
+// every access is one global load/store with an SGPR base and a VGPR offset
+// shared by all planes (the host guarantees planes are below 4 GiB).
 template <typename Real>
-__device__ __forceinline__ const Consts<Real> &consts_of(const DomDesc *d);
-template <>
-__device__ __forceinline__ const Consts<double> &consts_of<double>(const DomDesc *d) {
-  return d->cd;
+__device__ __forceinline__ Real ld(const NPL_GLOBAL Real *base, uint32_t boff) {
+  return *(const NPL_GLOBAL Real *)((const NPL_GLOBAL char *)base + boff);
 }
-template <>
-__device__ __forceinline__ const Consts<float> &consts_of<float>(const DomDesc *d) {
-  return d->cf;
+template <typename Real>
+__device__ __forceinline__ void st(NPL_GLOBAL Real *base, uint32_t boff, Real v) {
+  *(NPL_GLOBAL Real *)((NPL_GLOBAL char *)base + boff) = v;
 }
 
-template <int N, typename Real>
-__global__ void __launch_bounds__(kStepThreads) k_step(StepArgs a) {
+#ifndef NPL_WAVES_PER_EU
+#define NPL_KERNEL_ATTR
+#else
+#define NPL_KERNEL_ATTR __attribute__((amdgpu_waves_per_eu(NPL_WAVES_PER_EU)))
+#endif
+
+template <typename Real>
+__device__ __forceinline__ const NPL_CONST Consts<Real> *consts_of(const NPL_CONST DomDesc *d);
+template <>
+__device__ __forceinline__ const NPL_CONST Consts<double> *consts_of<double>(
+    const NPL_CONST DomDesc *d) {
+  return &d->cd;
+}
+template <>
+__device__ __forceinline__ const NPL_CONST Consts<float> *consts_of<float>(
+    const NPL_CONST DomDesc *d) {
+  return &d->cf;
+}
+
+// What one thread pulls for one node ahead of stage A and keeps until it
+// collides that node in stage C one iteration later.
+template <int M, typename Real>
+struct Pulled {
+  Real h[M][9];  // h[i][0] is the stored deviation of h_0, h[i][k>=1] streamed in
+  Real hi[M];    // stored phi_i of the previous step
+};
+// NS populations and previous velocity of the row being collided, loaded
+// one stage before use.
+template <typename Real>
+struct PulledNS {
+  Real g[9];   // g[1..8] streamed in (g[0] unused)
+  Real pu[2];  // stored u of the previous step
+};
+
+template <int N, typename Real, int kBW>
+__global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a) {
   constexpr int M = N - 1;
-  const StripDesc sd = a.strips[blockIdx.x];
+  typedef const NPL_GLOBAL Real *GIn;
+  typedef NPL_GLOBAL Real *GOut;
+  const NPL_CONST StripDesc *sp = (const NPL_CONST StripDesc *)a.strips + blockIdx.x;
+  StripDesc sd;
+  sd.dom = sp->dom;
+  sd.x0 = sp->x0;
+  sd.y0 = sp->y0;
+  sd.y1 = sp->y1;
+  sd.dir = sp->dir;
+  sd.x1 = sp->x1;
   if (sd.dom < 0) return;
-  const DomDesc *D = a.doms + sd.dom;
+  const NPL_CONST DomDesc *D = (const NPL_CONST DomDesc *)a.doms + sd.dom;
   if (a.substep >= D->steps_left) return;
   const int par = (a.substep + D->parity0) & 1;
-  const Real *__restrict__ hs = static_cast<const Real *>(D->h[par]);
-  Real *__restrict__ hd = static_cast<Real *>(D->h[par ^ 1]);
-  const Real *__restrict__ gs = static_cast<const Real *>(D->g[par]);
-  Real *__restrict__ gd = static_cast<Real *>(D->g[par ^ 1]);
-  const Real *__restrict__ pvs = static_cast<const Real *>(D->prev[par]);
-  Real *__restrict__ pvd = static_cast<Real *>(D->prev[par ^ 1]);
-  const Consts<Real> &K = consts_of<Real>(D);
-  const int nx = D->nx, ny = D->ny, pitch = D->pitch;
+  const GIn hs = (GIn)D->h[par];
+  const GOut hd = (GOut)D->h[par ^ 1];
+  const GIn gs = (GIn)D->g[par];
+  const GOut gd = (GOut)D->g[par ^ 1];
+  const GIn pvs = (GIn)D->prev[par];
+  const GOut pvd = (GOut)D->prev[par ^ 1];
+  const NPL_CONST Consts<Real> &K = *consts_of<Real>(D);
+  const int nx = D->nx, ny = D->ny;
   const bool wall = D->wall != 0;
-  const int64_t plane = D->plane;
+  // element strides between planes and between rows of each state group
+  const size_t psh = (size_t)D->ps[0], psg = (size_t)D->ps[1], psp = (size_t)D->ps[2];
+  const size_t rsh = (size_t)D->rs[0], rsg = (size_t)D->rs[1], rsp = (size_t)D->rs[2];
 
   __shared__ Real sphi[8][M][kBW];
   __shared__ Real sC[4][M][kBW];
 
   const int lane = threadIdx.x & (kBW - 1);
-  const int ry = threadIdx.x / kBW;
+  // the row handled by this wave (uniform; said explicitly so every row,
+  // bounce-back and plane decision stays in scalar registers)
+  const int ry = __builtin_amdgcn_readfirstlane(threadIdx.x / kBW);
   const int xl = sd.x0 - 2 + lane;
   int xc = xl % nx;
   if (xc < 0) xc += nx;
-  const int xw = xc == 0 ? nx - 1 : xc - 1;  // x - 1
-  const int xe = xc == nx - 1 ? 0 : xc + 1;  // x + 1
-  const int xend = min(sd.x0 + kTX, nx);
-  const bool interior = lane >= 2 && lane < kBW - 2 && xl < xend;
+  constexpr uint32_t SZ = sizeof(Real);
+  const uint32_t xcu = (uint32_t)xc * SZ;                              // byte offsets
+  const uint32_t xw = (xc == 0 ? (uint32_t)(nx - 1) : (uint32_t)xc - 1) * SZ;  // x - 1
+  const uint32_t xe = (xc == nx - 1 ? 0u : (uint32_t)xc + 1) * SZ;             // x + 1
+  const int ncol = sd.x1 - sd.x0;  // interior columns of this strip
+  const bool interior = lane >= 2 && lane < ncol + 2;
   const int H = sd.y1 - sd.y0;
   const int dir = sd.dir;
 
@@ -102,32 +160,31 @@ __global__ void __launch_bounds__(kStepThreads) k_step(StepArgs a) {
     return r;
   };
 
-  // Offset of the population k arriving at (xc, yp) in a set of 9-plane
-  // groups (CH) -- the source node x - c_k, or the node itself with the
-  // opposite direction when x - c_k lies beyond a wall.
+  // Sources of the populations arriving at (xc, yp): the node x - c_k, or
+  // the node itself with the opposite direction when x - c_k lies beyond a
+  // wall.  Rows and directions are uniform over the wave (scalar); only the
+  // column byte offset is per lane.
   struct Src {
-    int64_t o0, oS, oN;  // row offsets of yp, yp - 1, yp + 1 (wrapped)
-    bool bS, bN;         // bounce for c_y = +1 / c_y = -1
+    int y0, yS, yN;  // rows yp, yp - 1, yp + 1 (wrapped)
+    bool bS, bN;     // bounce for c_y = +1 / c_y = -1
   };
   auto make_src = [&](int yp) {
     Src s;
     const int yS = yp - 1, yN = yp + 1;
     s.bS = wall && yS < 0;
     s.bN = wall && yN >= ny;
-    s.o0 = (int64_t)yp * pitch;
-    s.oS = (int64_t)(yS < 0 ? yS + ny : yS) * pitch;
-    s.oN = (int64_t)(yN >= ny ? yN - ny : yN) * pitch;
+    s.y0 = yp;
+    s.yS = yS < 0 ? yS + ny : yS;
+    s.yN = yN >= ny ? yN - ny : yN;
     return s;
   };
-  // offset within one plane group for direction k (plane index returned
-  // separately so bounce-back can switch to the opposite direction)
-  auto src_off = [&](const Src &s, int k, int &kk) -> int64_t {
+  // source row (returned), direction kk and column byte offset co of k
+  auto src_of = [&](const Src &s, int k, int &kk, uint32_t &co) -> int {
     const int cx = cxk(k), cy = cyk(k);
     const bool b = (cy == 1 && s.bS) || (cy == -1 && s.bN);
     kk = b ? oppk(k) : k;
-    const int64_t ro = b ? s.o0 : (cy == 1 ? s.oS : (cy == -1 ? s.oN : s.o0));
-    const int co = b ? xc : (cx == 1 ? xw : (cx == -1 ? xe : xc));
-    return ro + co;
+    co = b ? xcu : (cx == 1 ? xw : (cx == -1 ? xe : xcu));
+    return b ? s.y0 : (cy == 1 ? s.yS : (cy == -1 ? s.yN : s.y0));
   };
 
   // lo part of phi_i: the stored deviation of h_0 plus the moving populations
@@ -138,27 +195,47 @@ __global__ void __launch_bounds__(kStepThreads) k_step(StepArgs a) {
     return lo;
   };
 
-  // ---- stage A: pull CH populations for march index mA, phi -> LDS ----
-  auto stageA = [&](int mA, Real (&cur)[M][9], Real (&hi)[M]) {
-    const int yp = phys_row(row_of(mA));
+  // ---- pull the CH populations and stored phi of march index m ----
+  auto pull_ch = [&](int m, Pulled<M, Real> &P) {
+    const int yp = phys_row(row_of(m));
     const Src s = make_src(yp);
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
       int kk;
-      const int64_t off = src_off(s, k, kk);
+      uint32_t co;
+      const int ys = src_of(s, k, kk, co);
 #pragma unroll
-      for (int i = 0; i < M; ++i) cur[i][k] = hs[(int64_t)(i * 9 + kk) * plane + off];
+      for (int i = 0; i < M; ++i)
+        P.h[i][k] = ld(hs + (size_t)(i * 9 + kk) * psh + (size_t)ys * rsh, co);
     }
 #pragma unroll
-    for (int i = 0; i < M; ++i) hi[i] = pvs[(int64_t)i * plane + s.o0 + xc];
+    for (int i = 0; i < M; ++i) P.hi[i] = ld(pvs + (size_t)i * psp + (size_t)yp * rsp, xcu);
+  };
+  // ---- pull the NS populations and stored u of march index m ----
+  auto pull_ns = [&](int m, PulledNS<Real> &Q) {
+    const int yp = phys_row(row_of(m));
+    const Src s = make_src(yp);
+#pragma unroll
+    for (int k = 1; k < 9; ++k) {
+      int kk;
+      uint32_t co;
+      const int ys = src_of(s, k, kk, co);
+      Q.g[k] = ld(gs + (size_t)(kk - 1) * psg + (size_t)ys * rsg, co);
+    }
+    Q.pu[0] = ld(pvs + (size_t)M * psp + (size_t)yp * rsp, xcu);
+    Q.pu[1] = ld(pvs + (size_t)(M + 1) * psp + (size_t)yp * rsp, xcu);
+  };
+
+  // ---- stage A: phi of march index mA -> LDS ----
+  auto stageA = [&](int mA, const Pulled<M, Real> &cur) {
     const int slot = (mA + 8) & 7;
 #pragma unroll
-    for (int i = 0; i < M; ++i) sphi[slot][i][lane] = hi[i] + lo_sum(cur[i]);  // eq:N28
+    for (int i = 0; i < M; ++i) sphi[slot][i][lane] = cur.hi[i] + lo_sum(cur.h[i]);  // eq:N28
   };
 
   // ---- stage B: chemical potentials for march index mB -> LDS ----
   auto stageB = [&](int mB) {
-    if (lane < 1 || lane > kBW - 2) return;
+    if (lane < 1 || lane > ncol + 2) return;
     int me = mB;
     if (wall) {
       const int r = row_of(mB);
@@ -199,8 +276,8 @@ __global__ void __launch_bounds__(kStepThreads) k_step(StepArgs a) {
     }
   };
 
-  // ---- stage C: collide march index mC with the populations in hh ----
-  auto stageC = [&](int mC, Real (&hh)[M][9], const Real (&hhi)[M]) {
+  // ---- stage C: collide march index mC with what was pulled for it ----
+  auto stageC = [&](int mC, const Pulled<M, Real> &P, const PulledNS<Real> &Q) {
     if (!interior || mC < 0 || mC >= H) return;
     const int yp = row_of(mC);
     const int p0 = (mC + 8) & 7, pN = (mC + dir + 8) & 7, pS = (mC - dir + 8) & 7;
@@ -258,15 +335,7 @@ __global__ void __launch_bounds__(kStepThreads) k_step(StepArgs a) {
       srcg = Real(1) - Real(0.5) * itau;
       theta = Real(1) / tm;
     }
-    // pull the moving NS populations
-    const Src s = make_src(yp);
-    Real g[9];
-#pragma unroll
-    for (int k = 1; k < 9; ++k) {
-      int kk;
-      const int64_t off = src_off(s, k, kk);
-      g[k] = gs[(int64_t)(kk - 1) * plane + off];
-    }
+    const Real(&g)[9] = Q.g;
     const Real irho = Real(1) / rho;
     const Real mx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
     const Real my = (g[2] - g[4]) + (g[5] + g[6]) - (g[7] + g[8]);
@@ -284,7 +353,9 @@ __global__ void __launch_bounds__(kStepThreads) k_step(StepArgs a) {
     // isotropic part of eq:N20_1: u.grad(rho) - tr(T) / (2 c_s^2)
     const Real gbase =
         udr - Real(1.5) * (Real(2) * uF + Real(2) / Real(3) * udr + theta * Ju);
-    const int64_t orow = (int64_t)yp * pitch + xc;
+    const GOut hrow = hd + (size_t)yp * rsh;
+    const GOut grow = gd + (size_t)yp * rsg;
+    const GOut prow = pvd + (size_t)yp * rsp;
 #pragma unroll
     for (int k = 1; k < 9; ++k) {
       const Real cx = Real(cxk(k)), cy = Real(cyk(k));
@@ -298,14 +369,13 @@ __global__ void __launch_bounds__(kStepThreads) k_step(StepArgs a) {
       const Real G =
           w * (gbase + Real(3) * cF +
                Real(4.5) * cu * (Real(2) * cF + Real(2) / Real(3) * cr + theta * cJ));
-      gd[(int64_t)(k - 1) * plane + orow] = g[k] - itau * (g[k] - geq) + srcg * G;
+      st(grow + (size_t)(k - 1) * psg, xcu, g[k] - itau * (g[k] - geq) + srcg * G);
     }
     // CH collisions
-    const Real pux = pvs[(int64_t)M * plane + orow];
-    const Real puy = pvs[(int64_t)(M + 1) * plane + orow];
+    const Real pux = Q.pu[0], puy = Q.pu[1];
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-      const Real pp = hhi[i];  // phi_i of the previous step (stored)
+      const Real pp = P.hi[i];  // phi_i of the previous step (stored)
       const Real psx = phi[i] * ux, psy = phi[i] * uy;
       const Real dx = psx - pp * pux, dy = psy - pp * puy;  // eq:N27
       const Real ec = K.eta_i[i] * Cv[i];
@@ -317,64 +387,148 @@ __global__ void __launch_bounds__(kStepThreads) k_step(StepArgs a) {
         const Real w = wk<Real>(k);
         const Real heq = w * (ec + Real(3) * (cx * psx + cy * psy));   // eq:N25
         const Real R = sr * w * Real(3) * (cx * dx + cy * dy);         // eq:N26
-        const Real hn = hh[i][k] - it * (hh[i][k] - heq) + R;
+        const Real hn = P.h[i][k] - it * (P.h[i][k] - heq) + R;
         hsum += hn;
-        hd[(int64_t)(i * 9 + k) * plane + orow] = hn;
+        st(hrow + (size_t)(i * 9 + k) * psh, xcu, hn);
       }
       // phi_i = hi + lo exactly; phi[i] = fl(hi + lo) is stored as the new
       // previous phi and the k = 0 slot keeps (hi + lo - phi[i]) - sum h_k
       // (error-free two-sum for the rounding part).
-      const Real lo = lo_sum(hh[i]);
+      const Real lo = lo_sum(P.h[i]);
       const Real bb = phi[i] - pp;
       const Real err = (pp - (phi[i] - bb)) + (lo - bb);
-      hd[(int64_t)(i * 9) * plane + orow] = err - hsum;
-      pvd[(int64_t)i * plane + orow] = phi[i];
+      st(hrow + (size_t)(i * 9) * psh, xcu, err - hsum);
+      st(prow + (size_t)i * psp, xcu, phi[i]);
     }
-    pvd[(int64_t)M * plane + orow] = ux;
-    pvd[(int64_t)(M + 1) * plane + orow] = uy;
+    st(prow + (size_t)M * psp, xcu, ux);
+    st(prow + (size_t)(M + 1) * psp, xcu, uy);
   };
 
-  Real bufA[M][9], bufB[M][9], hiA[M], hiB[M];
+  // Software pipeline over iterations j (march index mA = 2j - 2 + row):
+  //   phi(mA) -> LDS | barrier | issue NS pulls of mA - 2 and CH pulls of
+  //   mA + 2 | C(mA - 1) | barrier | collide mA - 2
+  // so the next row's CH loads are in flight during stage B and C.  Three
+  // register sets rotate: cur (pulled for mA), next (mA + 2), held (mA - 2).
   const int J = (H + 5) / 2;
-  for (int j = 0; j < J; j += 2) {
-    {
-      const int mA = 2 * j - 2 + ry;
-      stageA(mA, bufA, hiA);
-      __syncthreads();
-      stageB(mA - 1);
-      __syncthreads();
-      stageC(mA - 2, bufB, hiB);
-    }
-    {
-      const int mA = 2 * (j + 1) - 2 + ry;
-      stageA(mA, bufB, hiB);
-      __syncthreads();
-      stageB(mA - 1);
-      __syncthreads();
-      stageC(mA - 2, bufA, hiA);
-    }
+  PulledNS<Real> ns;
+#ifdef NPL_PIPELINE
+  Pulled<M, Real> bufA, bufB, bufC;
+  auto iteration = [&](int j, const Pulled<M, Real> &cur, Pulled<M, Real> &next,
+                       const Pulled<M, Real> &held) {
+    const int mA = 2 * j - 2 + ry;
+    stageA(mA, cur);
+    __syncthreads();
+    pull_ns(mA - 2, ns);
+    pull_ch(mA + 2, next);
+    stageB(mA - 1);
+    __syncthreads();
+    stageC(mA - 2, held, ns);
+  };
+  pull_ch(ry - 2, bufA);
+  for (int j = 0; j < J; j += 3) {  // j is uniform over the block
+    iteration(j, bufA, bufB, bufC);
+    if (j + 1 < J) iteration(j + 1, bufB, bufC, bufA);
+    if (j + 2 < J) iteration(j + 2, bufC, bufA, bufB);
   }
+#else
+  // two register sets: pulled for mA (cur) and for mA - 2 (held)
+  Pulled<M, Real> bufA, bufB;
+  auto iteration = [&](int j, Pulled<M, Real> &cur, const Pulled<M, Real> &held) {
+    const int mA = 2 * j - 2 + ry;
+    pull_ch(mA, cur);
+    stageA(mA, cur);
+    __syncthreads();
+    pull_ns(mA - 2, ns);
+    stageB(mA - 1);
+    __syncthreads();
+    stageC(mA - 2, held, ns);
+  };
+  for (int j = 0; j < J; j += 2) {  // j is uniform over the block
+    iteration(j, bufA, bufB);
+    if (j + 1 < J) iteration(j + 1, bufB, bufA);
+  }
+#endif
 }
 
-template <int N>
-static hipError_t launch_n(int precision, const StepArgs &a, int nblocks, hipStream_t st) {
-  if (precision == 64)
-    hipLaunchKernelGGL((k_step<N, double>), dim3(nblocks), dim3(kStepThreads), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_step<N, float>), dim3(nblocks), dim3(kStepThreads), 0, st, a);
+// LDS of one workgroup: rings of 8 phi rows and 4 C rows of (N-1) x BW values
+constexpr int lds_bytes(int N, int bytes, int bw) { return 12 * (N - 1) * bw * bytes; }
+// the widest row a (N, precision) pair is built for: at most 64 KiB of LDS
+constexpr int max_bw(int N, int bytes) {
+  return lds_bytes(N, bytes, 256) <= 65536 ? 256 : (lds_bytes(N, bytes, 128) <= 65536 ? 128 : 64);
+}
+
+int step_max_bw(int N, int precision) {
+  return max_bw(N, precision == 64 ? 8 : 4);
+}
+
+template <int N, int BW>
+static hipError_t launch_nb(int precision, const StepArgs &a, int nblocks, hipStream_t st) {
+  if (precision == 64) {
+    if constexpr (BW <= max_bw(N, 8))
+      hipLaunchKernelGGL((k_step<N, double, BW>), dim3(nblocks), dim3(BW * kRows), 0, st, a);
+    else
+      return hipErrorInvalidValue;
+  } else {
+    if constexpr (BW <= max_bw(N, 4))
+      hipLaunchKernelGGL((k_step<N, float, BW>), dim3(nblocks), dim3(BW * kRows), 0, st, a);
+    else
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_step(int N, int precision, const StepArgs &a, int nblocks, hipStream_t st) {
+template <int N>
+static hipError_t launch_n(int precision, int bw, const StepArgs &a, int nblocks,
+                           hipStream_t st) {
+  return bw == 256   ? launch_nb<N, 256>(precision, a, nblocks, st)
+         : bw == 128 ? launch_nb<N, 128>(precision, a, nblocks, st)
+                     : launch_nb<N, 64>(precision, a, nblocks, st);
+}
+
+template <int N, int BW>
+static int occ_nb(int precision) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+  if (precision == 64) {
+    if constexpr (BW <= max_bw(N, 8))
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<N, double, BW>, BW * kRows, 0);
+  } else {
+    if constexpr (BW <= max_bw(N, 4))
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<N, float, BW>, BW * kRows, 0);
+  }
+  return e == hipSuccess ? nb : 0;
+}
+
+template <int N>
+static int occ_n(int precision, int bw) {
+  return bw == 256 ? occ_nb<N, 256>(precision)
+                   : (bw == 128 ? occ_nb<N, 128>(precision) : occ_nb<N, 64>(precision));
+}
+
+int step_blocks_per_cu(int N, int precision, int bw) {
+  switch (N) {
+    case 2: return occ_n<2>(precision, bw);
+    case 3: return occ_n<3>(precision, bw);
+    case 4: return occ_n<4>(precision, bw);
+    case 5: return occ_n<5>(precision, bw);
+    case 6: return occ_n<6>(precision, bw);
+    case 7: return occ_n<7>(precision, bw);
+    case 8: return occ_n<8>(precision, bw);
+    default: return 0;
+  }
+}
+
+hipError_t launch_step(int N, int precision, int bw, const StepArgs &a, int nblocks,
+                       hipStream_t st) {
   if (nblocks <= 0) return hipSuccess;
   switch (N) {
-    case 2: return launch_n<2>(precision, a, nblocks, st);
-    case 3: return launch_n<3>(precision, a, nblocks, st);
-    case 4: return launch_n<4>(precision, a, nblocks, st);
-    case 5: return launch_n<5>(precision, a, nblocks, st);
-    case 6: return launch_n<6>(precision, a, nblocks, st);
-    case 7: return launch_n<7>(precision, a, nblocks, st);
-    case 8: return launch_n<8>(precision, a, nblocks, st);
+    case 2: return launch_n<2>(precision, bw, a, nblocks, st);
+    case 3: return launch_n<3>(precision, bw, a, nblocks, st);
+    case 4: return launch_n<4>(precision, bw, a, nblocks, st);
+    case 5: return launch_n<5>(precision, bw, a, nblocks, st);
+    case 6: return launch_n<6>(precision, bw, a, nblocks, st);
+    case 7: return launch_n<7>(precision, bw, a, nblocks, st);
+    case 8: return launch_n<8>(precision, bw, a, nblocks, st);
     default: return hipErrorInvalidValue;
   }
 }

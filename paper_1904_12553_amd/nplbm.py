@@ -17,7 +17,9 @@ from typing import Optional
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libnplbm.so")
+# NPLBM_LIB lets a developer point the binding at another build of the same
+# library (A/B timing of kernel variants); the default is the in-tree build.
+LIB_PATH = os.environ.get("NPLBM_LIB") or os.path.join(HERE, "libnplbm.so")
 
 NPLBM_OK = 0
 ERRORS = {-1: "EINVAL", -2: "ENOTSPD", -3: "ENOMEM", -4: "EDEVICE", -5: "ETOOBIG",

@@ -1,0 +1,64 @@
+"""Small driver for rocprofv3 runs (kernel traces and HBM counters).
+
+    python3 -m paper_1904_12553_amd.profile_run --what step --steps 10
+    python3 -m paper_1904_12553_amd.profile_run --what copy --mib 1024
+
+``step`` runs the benchmark workload (N=5, 2048 x 2048, FP32, the same
+launch configuration as bench.py) for a few eager steps; ``copy`` runs the
+library's plain copy kernel over a buffer of known size, whose FETCH_SIZE /
+WRITE_SIZE readings calibrate the counters, and prints the copy bandwidth
+measured with HIP events.
+"""
+import argparse
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--what", choices=["step", "copy"], default="step")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--side", type=int, default=2048)
+    ap.add_argument("--precision", type=int, default=32)
+    ap.add_argument("--mib", type=int, default=1024)
+    args = ap.parse_args()
+    import torch
+    import paper_1904_12553_amd as P
+    import workloads as W
+    torch.cuda.set_device(0)
+    if args.what == "copy":
+        n = args.mib << 20
+        a = torch.empty(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty(n, dtype=torch.uint8, device="cuda")
+        a.fill_(1)
+        for _ in range(3):
+            P.device_copy(b, a, n)
+        torch.cuda.synchronize()
+        st = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20
+        e0.record(st)
+        for _ in range(reps):
+            P.device_copy(b, a, n)
+        e1.record(st)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        print(json.dumps({"copy_bytes": n, "ms": ms, "GBps_read_plus_write": 2 * n / ms / 1e6}))
+        return
+    w = W.bands_and_droplets(args.side, accept=P.accepts)
+    d = P.Domain(precision=args.precision, **w.params())
+    d.set_fields(w.c, w.u)
+    os.environ["NPLBM_NO_GRAPH"] = "1"
+    d.step(args.steps)
+    d.sync()
+    print(json.dumps({"steps": args.steps, "nodes": w.nx * w.ny, "N": w.N,
+                      "precision": args.precision}))
+
+
+if __name__ == "__main__":
+    main()
