@@ -96,7 +96,7 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=500)
     ap.add_argument("--acc-steps", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=96)
     ap.add_argument("--serving-steps-scale", type=float, default=0.1)

@@ -2,6 +2,8 @@
 // fields, FP64 conservation / Laplace reductions and a plain copy kernel.
 // None of these run inside the time loop except the diagnostics, which the
 // caller invokes every K steps.
+#include <algorithm>
+
 #include "lattice.h"
 #include "nplbm_internal.h"
 
@@ -349,10 +351,11 @@ __global__ void k_laplace_final(const double *partials, int nblk, double *out) {
   out[0] = (a[1] > 0.0 && a[3] > 0.0) ? a[0] / a[1] - a[2] / a[3] : 0.0;
 }
 
+// one 16-byte element per thread and a grid covering the buffer: the
+// fastest plain copy pattern measured on gfx950 (~6.2 TB/s read + write)
 __global__ void k_copy16(uint4 *__restrict__ dst, const uint4 *__restrict__ src, int64_t n16) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
-       i += (int64_t)gridDim.x * blockDim.x)
-    dst[i] = src[i];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n16) dst[i] = src[i];
 }
 
 __global__ void k_copy1(unsigned char *dst, const unsigned char *src, int64_t n) {
@@ -444,11 +447,13 @@ hipError_t launch_laplace(const double *p, int nx, int ny, double xc, double yc,
 hipError_t launch_copy(void *dst, const void *src, size_t nbytes, hipStream_t st) {
   const bool aligned = (((uintptr_t)dst | (uintptr_t)src) & 15) == 0;
   const int64_t n16 = aligned ? (int64_t)(nbytes / 16) : 0;
-  if (n16 > 0) {
-    int64_t nb = (n16 + kThreads - 1) / kThreads;
-    if (nb > 8192) nb = 8192;
+  for (int64_t done = 0; done < n16;) {  // chunks of at most 2^30 elements
+    const int64_t cnt = std::min<int64_t>(n16 - done, (int64_t)1 << 30);
+    const int64_t nb = (cnt + kThreads - 1) / kThreads;
     hipLaunchKernelGGL(k_copy16, dim3((unsigned)nb), dim3(kThreads), 0, st,
-                       static_cast<uint4 *>(dst), static_cast<const uint4 *>(src), n16);
+                       static_cast<uint4 *>(dst) + done, static_cast<const uint4 *>(src) + done,
+                       cnt);
+    done += cnt;
   }
   const int64_t rest = (int64_t)nbytes - n16 * 16;
   if (rest > 0)
