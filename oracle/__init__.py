@@ -19,6 +19,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
 
+
 ORC_OK, ORC_EINVAL, ORC_ENOTSPD, ORC_ENOMEM = 0, -1, -2, -3
 
 

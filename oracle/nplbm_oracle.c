@@ -433,14 +433,14 @@ static void macroscopic(orc_sim *s) {
   size_t n = (size_t)nx * ny;
   /* eq:N28 */
   for (int i = 0; i < n1; ++i)
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (s->nx * s->ny >= 8192)
     for (size_t x = 0; x < n; ++x) {
       double a = 0.0;
       for (int k = 0; k < Q; ++k) a += s->h[((size_t)i * Q + k) * n + x];
       s->phi[(size_t)i * n + x] = a;
     }
   /* closure and tau_g */
-  #pragma omp parallel for schedule(static)
+  #pragma omp parallel for schedule(static) if (s->nx * s->ny >= 8192)
   for (size_t x = 0; x < n; ++x) {
     double ph[NMAX], cc[NMAX], r;
     for (int i = 0; i < n1; ++i) ph[i] = s->phi[(size_t)i * n + x];
@@ -453,12 +453,12 @@ static void macroscopic(orc_sim *s) {
   }
   /* Laplacians and chemical potentials */
   for (int i = 0; i < n1; ++i)
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (s->nx * s->ny >= 8192)
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x)
         s->lap[(size_t)i * n + (size_t)y * nx + x] =
             laplacian(s, s->phi + (size_t)i * n, x, y);
-  #pragma omp parallel for schedule(static)
+  #pragma omp parallel for schedule(static) if (s->nx * s->ny >= 8192)
   for (size_t x = 0; x < n; ++x) {
     double cc[NMAX], hi[NMAX];
     for (int k = 0; k < N; ++k) cc[k] = s->c[(size_t)k * n + x];
@@ -470,7 +470,7 @@ static void macroscopic(orc_sim *s) {
     }
   }
   /* gradients */
-  #pragma omp parallel for schedule(static)
+  #pragma omp parallel for schedule(static) if (s->nx * s->ny >= 8192)
   for (int y = 0; y < ny; ++y)
     for (int x = 0; x < nx; ++x) {
       size_t id = (size_t)y * nx + x;
@@ -483,7 +483,7 @@ static void macroscopic(orc_sim *s) {
       grad(s, s->rho, x, y, &s->grho[id], &s->grho[n + id]);
     }
   /* forces, flux, velocity, pressure */
-  #pragma omp parallel for schedule(static)
+  #pragma omp parallel for schedule(static) if (s->nx * s->ny >= 8192)
   for (size_t x = 0; x < n; ++x) {
     double Fx = 0.0, Fy = 0.0, Jx = 0.0, Jy = 0.0;
     for (int i = 0; i < n1; ++i) {
@@ -522,7 +522,7 @@ static void stream(orc_sim *s, const double *src, double *dst, int nfields) {
   static const int OPP[Q] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
   for (int f = 0; f < nfields; ++f)
     for (int k = 0; k < Q; ++k)
-      #pragma omp parallel for schedule(static)
+      #pragma omp parallel for schedule(static) if (s->nx * s->ny >= 8192)
       for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
           double v = src[((size_t)f * Q + k) * n + (size_t)y * nx + x];
@@ -597,7 +597,7 @@ int orc_step(orc_sim *s, long nsteps) {
   size_t n = (size_t)s->nx * s->ny;
   for (long it = 0; it < nsteps; ++it) {
     macroscopic(s);
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (s->nx * s->ny >= 8192)
     for (size_t x = 0; x < n; ++x) {
       double ux = s->u[x], uy = s->u[n + x], r = s->rho[x], p = s->p[x];
       double tg = s->taug[x];

@@ -1,0 +1,104 @@
+"""The C-ABI library without a GPU: it loads, exports every symbol declared in
+include/nplbm.h, and its host-only calls (parameter validation, the eq:N14
+solve, the footprint) behave as documented.  No compute call is made."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_1904_12553_amd import nplbm
+    return nplbm
+
+
+def test_library_exports_every_declared_symbol():
+    nb = _lib()
+    L = nb.lib()
+    hdr = open(os.path.join(ROOT, "include", "nplbm.h")).read()
+    declared = set(re.findall(r"\b(nplbm_[a-z_]+)\s*\(", hdr))
+    assert declared, "no declarations found"
+    assert declared == set(nb.EXPORTS)
+    for name in declared:
+        assert getattr(L, name) is not None
+
+
+def test_validate_lambda_matches_closed_form():
+    nb = _lib()
+    lam, b2, K = nb.validate(3, W.uniform_sigma(3, 1e-3), np.ones(3))
+    assert np.allclose(lam, [[2e-3, -1e-3], [-1e-3, 2e-3]], rtol=1e-13)
+    assert b2 == pytest.approx(6e-3, rel=1e-14)
+    assert K == pytest.approx(3e-3, rel=1e-14)
+
+
+@pytest.mark.parametrize("N", [3, 4, 5])
+def test_validate_matches_oracle_lambda(N):
+    """The library's eq:N14 solve (complete pivoting, L from phase jumps)
+    agrees with the oracle's (partial pivoting, L from eq:N15-N16)."""
+    from oracle import OracleSim
+    from oracle.accept import oracle_accepts
+    rng = np.random.default_rng(N)
+    rho = rng.uniform(1, 3, N)
+    sig, _ = W.draw_sigma(N, 77 + N, accept=oracle_accepts, rho=rho)
+    lam, b2, K = _lib().validate(N, sig, rho)
+    lo, b2o, Ko, _ = OracleSim(N, 4, 4, sig, rho, np.ones(N)).lam()
+    assert np.allclose(lam, lo, rtol=1e-10, atol=1e-16)
+    assert b2 == pytest.approx(b2o, rel=1e-14)
+
+
+def test_validate_rejects_bad_parameters():
+    nb = _lib()
+    ok = dict(N=3, sigma=W.uniform_sigma(3, 1e-3), rho=np.ones(3))
+    with pytest.raises(nb.NplbmError) as e:
+        nb.validate(3, W.uniform_sigma(3, 1e-3), np.array([1.0, -1.0, 1.0]))
+    assert e.value.code == -1
+    with pytest.raises(nb.NplbmError) as e:
+        nb.validate(3, W.uniform_sigma(3, 1e-3), np.ones(3), tau_phi=0.5)
+    assert e.value.code == -1
+    sig = W.uniform_sigma(3, 1e-3)
+    sig[0, 1] = 2e-3  # asymmetric
+    with pytest.raises(nb.NplbmError) as e:
+        nb.validate(3, sig, np.ones(3))
+    assert e.value.code == -1
+    bad = np.array([[0, 1e-3, 1e-3], [1e-3, 0, 5e-3], [1e-3, 5e-3, 0]])
+    with pytest.raises(nb.NplbmError) as e:
+        nb.validate(3, bad, np.ones(3))
+    assert e.value.code == -2
+    with pytest.raises(nb.NplbmError) as e:
+        nb.validate(9, W.uniform_sigma(9, 1e-3), np.ones(9))
+    assert e.value.code == -1
+
+
+def test_accepts_agrees_with_oracle():
+    nb = _lib()
+    from oracle.accept import oracle_accepts
+    rng = np.random.default_rng(5)
+    agree = 0
+    for t in range(40):
+        N = int(rng.integers(3, 6))
+        rho = rng.uniform(1, 3, N)
+        sig, _ = W.draw_sigma(N, 1000 + t, rho=rho)
+        assert nb.accepts(sig, rho) == oracle_accepts(sig, rho)
+        agree += 1
+    assert agree == 40
+
+
+def test_footprint_scales_with_precision_and_size():
+    nb = _lib()
+    w = W.static_droplet()
+    f64 = nb.footprint(precision=64, **w.params())
+    f32 = nb.footprint(precision=32, **w.params())
+    assert f64 > f32 > 0
+    # persistent state: two copies of 10N values per node plus prev, i.e.
+    # more than 2 * (9(N-1) + 8) * n * s bytes
+    n = w.nx * w.ny
+    assert f32 > 2 * (9 * 2 + 8) * n * 4
+    big = dict(w.params(), nx=2 * w.nx)
+    assert nb.footprint(precision=32, **big) > 1.8 * f32
+    bad = dict(w.params(), rho=np.array([1.0, 0.0, 1.0]))
+    assert nb.footprint(precision=32, **bad) == 0

@@ -1,0 +1,207 @@
+"""Physics pins of the FP64 oracle: statements the paper makes (or that
+follow from its equations) about whole runs.
+
+* flat interface: the tanh profile of width W (the paper's initial profile,
+  eq:N31_a) is the discrete equilibrium of a two-phase interface with
+  sigma = sigma_min (reading of the factor 2 in eq:N11 vs eq:N17), with
+  second-order discretisation error;
+* Laplace law for a static droplet (Sec. 4.1): Delta p R / sigma -> 1;
+* two-phase reduction (Sec. 4.1): the N=3 model with phase 3 absent follows
+  the N=2 model when the mobility is doubled (derived: phi^(2) = 2 c_1 - 1
+  while phi_1^(3) = c_1);
+* liquid lens (Sec. 4.2): equilibrium contact angles against the Neumann
+  triangle, eq:N32.
+These take seconds to a minute of CPU each.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import OracleSim
+
+
+def _flat_profile(nx, W_, x1, x2):
+    x = np.arange(nx, dtype=float)
+    return 0.5 * (np.tanh(2.0 * (x - x1) / W_) - np.tanh(2.0 * (x - x2) / W_))
+
+
+def _flat_error(W_, steps):
+    nx, ny = int(16 * W_), 4
+    prof = _flat_profile(nx, W_, nx / 4, 3 * nx / 4)
+    c2 = np.tile(prof, (ny, 1))
+    c = np.stack([1.0 - c2, c2])
+    s = OracleSim(2, nx, ny, W.uniform_sigma(2, 1e-3), np.ones(2), np.full(2, 0.1),
+                  mobility=0.1, tau_phi=0.8, W=W_)
+    s.init(c)
+    s.step(steps)
+    cc, u, p = s.macro()
+    return np.max(np.abs(cc[1] - c2))
+
+
+def test_flat_interface_is_equilibrium_second_order():
+    e4 = _flat_error(4.0, 3000)
+    e8 = _flat_error(8.0, 3000)
+    # with h twice as large (H of eq:N11 taken literally) the interface would
+    # sharpen by sqrt(2) and the profile would move by ~0.1
+    assert e4 < 5e-3
+    assert e8 < e4 / 3.0   # second order: ~4x smaller at twice the width
+
+
+@pytest.mark.parametrize("rho", [(1.0, 1.0, 1.0), (1.0, 2.5, 1.7)])
+@pytest.mark.parametrize("pair", [(0, 1), (0, 2), (1, 2)])
+def test_flat_interface_width_follows_each_tension(pair, rho):
+    """N=3: a flat k|l interface with sigma_kl = 1.5 sigma_min (the absent
+    phase m has sigma_km = sigma_lm = sigma_min, so it is not drawn into the
+    interface) has the equilibrium profile 1/2 + 1/2 tanh(2 x / W_kl) with
+    W_kl = W sigma_kl / sigma_min (derived from eq:N14 with the L vectors of
+    eq:N15-N16, eq:N17 and eq:N36), for any densities; that profile stays
+    put, while the profile of width W relaxes visibly.  A wrong mixing matrix
+    for unequal tensions would give another width."""
+    k, l = pair
+    m = 3 - k - l
+    sig = np.full((3, 3), 1.0e-3)
+    np.fill_diagonal(sig, 0.0)
+    sig[k, l] = sig[l, k] = 1.5e-3
+    rho = np.asarray(rho)
+    nx, ny = 96, 4
+
+    def run(width):
+        prof = np.tile(_flat_profile(nx, width, nx / 4, 3 * nx / 4), (ny, 1))
+        c = np.zeros((3, ny, nx))
+        c[l] = prof
+        c[k] = 1.0 - prof
+        s = OracleSim(3, nx, ny, sig, rho, 0.1 * rho, mobility=0.1, tau_phi=0.8, W=4.0)
+        s.init(c)
+        s.step(3000)
+        cc, _, _ = s.macro()
+        return np.max(np.abs(cc[l] - prof)), np.max(np.abs(cc[m]))
+
+    err, absent = run(4.0 * 1.5)
+    assert err < 2.5e-3
+    assert absent < 1e-3
+    err_w, _ = run(4.0)
+    assert err_w > 4 * err
+
+
+def test_laplace_law_static_droplet():
+    """N=3 static droplet (phase 2 disc, phase 3 absent), sigma = 1e-3,
+    tau_g = 1: the bulk pressure jump, averaged over acoustic oscillations,
+    equals sigma / R with R from the droplet area.  With W = 4 and R = 25 the
+    diffuse interface lowers Delta p R / sigma by ~3% (0.97 / 0.98 at R = 50 /
+    100 on the same lattice, i.e. the gap closes as W / R -> 0)."""
+    w = W.static_droplet()
+    s = OracleSim(**w.params())
+    s.init(w.c, w.u)
+    s.step(3000)
+    y, x = np.mgrid[0:w.ny, 0:w.nx]
+    r = np.hypot(x - 50.0, y - 50.0)
+    jumps, radii = [], []
+    for _ in range(60):
+        s.step(25)
+        c, u, p = s.macro()
+        jumps.append(p[r <= 25 - 8].mean() - p[r >= 25 + 8].mean())
+        radii.append(np.sqrt(c[1].sum() / np.pi))
+    dp, R = np.mean(jumps), np.mean(radii)
+    assert dp * R / 1e-3 == pytest.approx(1.0, abs=0.05)
+
+
+def test_two_phase_reduction():
+    """N=3 with c_3 = 0 (equal densities and tensions) against N=2 with twice
+    the mobility: the droplet fractions agree and phase 3 stays absent up to
+    the small leakage of the weakly compressible flow."""
+    n = 64
+    w3 = W.static_droplet(n, n, R=16.0, steps=1000)
+    w2 = W.two_phase_droplet(n, n, R=16.0, mobility=0.2)
+    a = OracleSim(**w3.params())
+    b = OracleSim(**w2.params())
+    a.init(w3.c)
+    b.init(w2.c)
+    a.step(1000)
+    b.step(1000)
+    ca, _, _ = a.macro()
+    cb, _, _ = b.macro()
+    assert np.max(np.abs(ca[2])) < 1e-4
+    assert np.max(np.abs(ca[1] - cb[1])) < 1e-4
+    # halving the N=2 mobility instead breaks the agreement visibly
+    b2 = OracleSim(**dict(w2.params(), mobility=0.1))
+    b2.init(w2.c)
+    b2.step(1000)
+    cb2, _, _ = b2.macro()
+    assert np.max(np.abs(ca[1] - cb2[1])) > 3 * np.max(np.abs(ca[1] - cb[1]))
+
+
+def _lens(nx, ny, R, s12, s13, s23, rho=(1.0, 1.0, 1.0)):
+    """Phase 1 lens at the centre of a flat phase-2 (top) / phase-3 (bottom)
+    interface (eq:N35 pattern), walls in y."""
+    xc, yc = nx / 2.0, ny / 2.0
+    cl = W.disc(nx, ny, xc, yc, R, 4.0)
+    x, y = W.grid(nx, ny)
+    ct = np.maximum(0.5 + 0.5 * np.tanh(2.0 * (y - yc) / 4.0) - cl, 0.0)
+    c = np.stack([cl, ct, 1.0 - cl - ct])
+    sig = np.array([[0.0, s12, s13], [s12, 0.0, s23], [s13, s23, 0.0]])
+    rho = np.asarray(rho)
+    return c, dict(N=3, nx=nx, ny=ny, sigma=sig, rho=rho, mu=0.1 * rho, mobility=0.1,
+                   tau_phi=0.8, W=4.0, wall_y=True)
+
+
+def lens_angles(c):
+    """Contact angles (degrees) of the upper (phase 1|2) and lower (1|3) lens
+    arcs against the flat 2|3 interface: least-squares circles through the
+    c_1 = 1/2 contour, middle 70% of each arc (away from the diffuse triple
+    junctions); the angle is that of the circle where it meets the level of
+    the flat interface far from the lens."""
+    c1 = c[0]
+    ny, nx = c1.shape
+    col = c[1][:, 0]
+    j = np.where((col[:-1] < 0.5) & (col[1:] >= 0.5))[0][0]
+    yf = j + (0.5 - col[j]) / (col[j + 1] - col[j])
+
+    def arc(upper):
+        pts = []
+        for x in range(nx):
+            v = c1[:, x]
+            if v.max() < 0.5:
+                continue
+            idx = np.where(v >= 0.5)[0]
+            if upper:
+                q = idx[-1]
+                if q + 1 < ny:
+                    yy = q + (v[q] - 0.5) / (v[q] - v[q + 1])
+                    if yy > yf + 2:
+                        pts.append((x, yy))
+            else:
+                q = idx[0]
+                if q >= 1:
+                    yy = q - (v[q] - 0.5) / (v[q] - v[q - 1])
+                    if yy < yf - 2:
+                        pts.append((x, yy))
+        P = np.array(pts)
+        xm, hw = 0.5 * (P[:, 0].min() + P[:, 0].max()), 0.5 * (P[:, 0].max() - P[:, 0].min())
+        P = P[np.abs(P[:, 0] - xm) <= 0.7 * hw]
+        A = np.stack([P[:, 0], P[:, 1], np.ones(len(P))], 1)
+        a, b, cc = np.linalg.lstsq(A, P[:, 0] ** 2 + P[:, 1] ** 2, rcond=None)[0]
+        return a / 2, b / 2, np.sqrt(cc + a * a / 4 + b * b / 4)
+
+    _, yu, ru = arc(True)
+    _, yl, rl = arc(False)
+    return (np.degrees(np.arccos((yf - yu) / ru)), np.degrees(np.arccos((yl - yf) / rl)))
+
+
+def neumann_angles(s12, s13, s23):
+    """eq:N32."""
+    t1 = np.degrees(np.arccos((s12 ** 2 + s23 ** 2 - s13 ** 2) / (2 * s12 * s23)))
+    t2 = np.degrees(np.arccos((s13 ** 2 + s23 ** 2 - s12 ** 2) / (2 * s13 * s23)))
+    return t1, t2
+
+
+def test_liquid_lens_equal_tensions_neumann():
+    """Sec. 4.2 with sigma_12 : sigma_13 : sigma_23 = 1 : 1 : 1: both contact
+    angles go to 60 degrees (eq:N32; the paper measures 60.7, Table 1)."""
+    c, kw = _lens(100, 100, 20.0, 0.01, 0.01, 0.01)
+    s = OracleSim(**kw)
+    s.init(c)
+    s.step(12000)
+    cc, _, _ = s.macro()
+    t1, t2 = lens_angles(cc)
+    n1, n2 = neumann_angles(0.01, 0.01, 0.01)
+    assert abs(t1 - n1) < 2.5 and abs(t2 - n2) < 2.5
