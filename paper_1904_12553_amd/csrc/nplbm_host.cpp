@@ -340,7 +340,8 @@ Layout plan_layout(const nplbm_params *p) {
   Layout L;
   const int N = p->N, M = N - 1;
   const size_t s = p->precision == 64 ? 8 : 4;
-  L.pitch = (p->nx + 15) & ~15;
+  L.pitch = (p->nx + 31) & ~31;  // rows start on 128-byte lines
+  if (const char *e = std::getenv("NPLBM_PITCH_PAD")) L.pitch += std::max(0, std::atoi(e)) & ~31;
   const size_t n = (size_t)p->nx * p->ny;
   const int np[3] = {M * 9, 8, M + 2};  // planes per group
   const char *lay = std::getenv("NPLBM_LAYOUT");

@@ -59,9 +59,15 @@ template <typename Real>
 __device__ __forceinline__ Real ld(const NPL_GLOBAL Real *base, uint32_t boff) {
   return *(const NPL_GLOBAL Real *)((const NPL_GLOBAL char *)base + boff);
 }
+// Stores of the new state are never read again within the step; FP64 runs
+// measured faster with them marked nontemporal (streaming), FP32 slower.
 template <typename Real>
 __device__ __forceinline__ void st(NPL_GLOBAL Real *base, uint32_t boff, Real v) {
-  *(NPL_GLOBAL Real *)((NPL_GLOBAL char *)base + boff) = v;
+  NPL_GLOBAL Real *p = (NPL_GLOBAL Real *)((NPL_GLOBAL char *)base + boff);
+  if constexpr (sizeof(Real) == 8)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
 }
 
 #ifndef NPL_WAVES_PER_EU
@@ -404,50 +410,54 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
     st(prow + (size_t)(M + 1) * psp, xcu, uy);
   };
 
-  // Software pipeline over iterations j (march index mA = 2j - 2 + row):
-  //   phi(mA) -> LDS | barrier | issue NS pulls of mA - 2 and CH pulls of
-  //   mA + 2 | C(mA - 1) | barrier | collide mA - 2
-  // so the next row's CH loads are in flight during stage B and C.  Three
-  // register sets rotate: cur (pulled for mA), next (mA + 2), held (mA - 2).
+  // March over iterations j (march index mA = 2j - 2 + row).  Each does
+  //   phi(mA) -> LDS | barrier | NS pulls of mA - 2 | C(mA - 1) | barrier |
+  //   collide mA - 2
+  // with the CH pulls of row mA held in registers until their collision two
+  // iterations later.  FP32 up to N = 5 has the registers to pipeline one
+  // more set: the CH pulls of mA + 2 are issued right after the first
+  // barrier, so they are in flight during stages B and C (three sets rotate:
+  // cur = mA, next = mA + 2, held = mA - 2).  FP64 and larger N keep two
+  // sets and their occupancy; three would halve it or spill.
   const int J = (H + 5) / 2;
   PulledNS<Real> ns;
-#ifdef NPL_PIPELINE
-  Pulled<M, Real> bufA, bufB, bufC;
-  auto iteration = [&](int j, const Pulled<M, Real> &cur, Pulled<M, Real> &next,
-                       const Pulled<M, Real> &held) {
-    const int mA = 2 * j - 2 + ry;
-    stageA(mA, cur);
-    __syncthreads();
-    pull_ns(mA - 2, ns);
-    pull_ch(mA + 2, next);
-    stageB(mA - 1);
-    __syncthreads();
-    stageC(mA - 2, held, ns);
-  };
-  pull_ch(ry - 2, bufA);
-  for (int j = 0; j < J; j += 3) {  // j is uniform over the block
-    iteration(j, bufA, bufB, bufC);
-    if (j + 1 < J) iteration(j + 1, bufB, bufC, bufA);
-    if (j + 2 < J) iteration(j + 2, bufC, bufA, bufB);
+  constexpr bool kPipeline = sizeof(Real) == 4 && N <= 5;
+  if constexpr (kPipeline) {
+    Pulled<M, Real> bufA, bufB, bufC;
+    auto iteration = [&](int j, const Pulled<M, Real> &cur, Pulled<M, Real> &next,
+                         const Pulled<M, Real> &held) {
+      const int mA = 2 * j - 2 + ry;
+      stageA(mA, cur);
+      __syncthreads();
+      pull_ns(mA - 2, ns);
+      pull_ch(mA + 2, next);
+      stageB(mA - 1);
+      __syncthreads();
+      stageC(mA - 2, held, ns);
+    };
+    pull_ch(ry - 2, bufA);
+    for (int j = 0; j < J; j += 3) {  // j is uniform over the block
+      iteration(j, bufA, bufB, bufC);
+      if (j + 1 < J) iteration(j + 1, bufB, bufC, bufA);
+      if (j + 2 < J) iteration(j + 2, bufC, bufA, bufB);
+    }
+  } else {
+    Pulled<M, Real> bufA, bufB;  // pulled for mA (cur) and for mA - 2 (held)
+    auto iteration = [&](int j, Pulled<M, Real> &cur, const Pulled<M, Real> &held) {
+      const int mA = 2 * j - 2 + ry;
+      pull_ch(mA, cur);
+      stageA(mA, cur);
+      __syncthreads();
+      pull_ns(mA - 2, ns);
+      stageB(mA - 1);
+      __syncthreads();
+      stageC(mA - 2, held, ns);
+    };
+    for (int j = 0; j < J; j += 2) {  // j is uniform over the block
+      iteration(j, bufA, bufB);
+      if (j + 1 < J) iteration(j + 1, bufB, bufA);
+    }
   }
-#else
-  // two register sets: pulled for mA (cur) and for mA - 2 (held)
-  Pulled<M, Real> bufA, bufB;
-  auto iteration = [&](int j, Pulled<M, Real> &cur, const Pulled<M, Real> &held) {
-    const int mA = 2 * j - 2 + ry;
-    pull_ch(mA, cur);
-    stageA(mA, cur);
-    __syncthreads();
-    pull_ns(mA - 2, ns);
-    stageB(mA - 1);
-    __syncthreads();
-    stageC(mA - 2, held, ns);
-  };
-  for (int j = 0; j < J; j += 2) {  // j is uniform over the block
-    iteration(j, bufA, bufB);
-    if (j + 1 < J) iteration(j + 1, bufB, bufA);
-  }
-#endif
 }
 
 // LDS of one workgroup: rings of 8 phi rows and 4 C rows of (N-1) x BW values
