@@ -1,0 +1,116 @@
+"""Measurements of whole-run physics shared by the oracle and GPU physics
+tests: lens set-up (eq:N35 pattern), contact angles and lens geometry
+(Sec. 4.2, eq:N32-N34).  Plain NumPy on fields read back as FP64."""
+import numpy as np
+
+import workloads as W
+
+
+def lens_setup(nx, ny, R, s12, s13, s23, rho=(1.0, 1.0, 1.0), W_=4.0):
+    """Phase 1 lens of radius R at the centre of a flat phase-2 (top) /
+    phase-3 (bottom) interface (eq:N35), walls in y, tau_g = tau_i = 0.8
+    (mu = 0.1 rho), m = 0.1."""
+    xc, yc = nx / 2.0, ny / 2.0
+    cl = W.disc(nx, ny, xc, yc, R, W_)
+    x, y = W.grid(nx, ny)
+    ct = np.maximum(0.5 + 0.5 * np.tanh(2.0 * (y - yc) / W_) - cl, 0.0)
+    c = np.stack([cl, ct, 1.0 - cl - ct])
+    sig = np.array([[0.0, s12, s13], [s12, 0.0, s23], [s13, s23, 0.0]])
+    rho = np.asarray(rho, dtype=float)
+    return c, dict(N=3, nx=nx, ny=ny, sigma=sig, rho=rho, mu=0.1 * rho, mobility=0.1,
+                   tau_phi=0.8, W=W_, wall_y=True)
+
+
+def flat_level(c):
+    """Level of the flat 2|3 interface far from the lens (column x = 0):
+    where c_2 crosses 1/2, linearly interpolated."""
+    col = c[1][:, 0]
+    j = np.where((col[:-1] < 0.5) & (col[1:] >= 0.5))[0][0]
+    return j + (0.5 - col[j]) / (col[j + 1] - col[j])
+
+
+def _arc_points(c1, yf, upper):
+    ny, nx = c1.shape
+    pts = []
+    for x in range(nx):
+        v = c1[:, x]
+        if v.max() < 0.5:
+            continue
+        idx = np.where(v >= 0.5)[0]
+        if upper:
+            q = idx[-1]
+            if q + 1 < ny:
+                yy = q + (v[q] - 0.5) / (v[q] - v[q + 1])
+                if yy > yf + 2:
+                    pts.append((x, yy))
+        else:
+            q = idx[0]
+            if q >= 1:
+                yy = q - (v[q] - 0.5) / (v[q] - v[q - 1])
+                if yy < yf - 2:
+                    pts.append((x, yy))
+    return np.array(pts)
+
+
+def lens_angles(c):
+    """Contact angles (degrees) of the upper (phase 1|2) and lower (1|3) lens
+    arcs against the flat 2|3 interface: least-squares circles through the
+    c_1 = 1/2 contour, middle 70% of each arc (away from the diffuse triple
+    junctions); the angle is that of the circle where it meets the level of
+    the flat interface far from the lens."""
+    c1 = c[0]
+    yf = flat_level(c)
+
+    def circle(upper):
+        P = _arc_points(c1, yf, upper)
+        xm, hw = 0.5 * (P[:, 0].min() + P[:, 0].max()), 0.5 * (P[:, 0].max() - P[:, 0].min())
+        P = P[np.abs(P[:, 0] - xm) <= 0.7 * hw]
+        A = np.stack([P[:, 0], P[:, 1], np.ones(len(P))], 1)
+        a, b, cc = np.linalg.lstsq(A, P[:, 0] ** 2 + P[:, 1] ** 2, rcond=None)[0]
+        return a / 2, b / 2, np.sqrt(cc + a * a / 4 + b * b / 4)
+
+    _, yu, ru = circle(True)
+    _, yl, rl = circle(False)
+    return (np.degrees(np.arccos((yf - yu) / ru)), np.degrees(np.arccos((yl - yf) / rl)))
+
+
+def lens_geometry(c):
+    """The paper's lens measures (Sec. 4.2): length d between the triple
+    junctions, cap heights h_1 (above the flat interface, into phase 2) and
+    h_2 (below, into phase 3), the angles theta_i = 2 atan(2 h_i / d), and
+    the lens area A (nodes with c_1 >= 1/2).  On the c_1 = 1/2 contour:
+    h_i from the extreme crossings of the columns, d from the crossings of
+    the row interpolated to the flat-interface level."""
+    c1 = c[0]
+    yf = flat_level(c)
+    up = _arc_points(c1, yf, True)
+    lo = _arc_points(c1, yf, False)
+    h1 = up[:, 1].max() - yf
+    h2 = yf - lo[:, 1].min()
+    j = int(np.floor(yf))
+    t = yf - j
+    row = (1.0 - t) * c1[j] + t * c1[j + 1]
+    inside = np.where(row >= 0.5)[0]
+    a, b = inside[0], inside[-1]
+    xl = a - (row[a] - 0.5) / (row[a] - row[a - 1])
+    xr = b + (row[b] - 0.5) / (row[b] - row[b + 1])
+    d = xr - xl
+    th = np.degrees(2.0 * np.arctan(2.0 * np.array([h1, h2]) / d))
+    return dict(d=d, h1=h1, h2=h2, theta1=th[0], theta2=th[1], A=float((c1 >= 0.5).sum()))
+
+
+def neumann_angles(s12, s13, s23):
+    """Equilibrium contact angles (degrees) from the tensions, eq:N32."""
+    t1 = np.degrees(np.arccos((s12 ** 2 + s23 ** 2 - s13 ** 2) / (2 * s12 * s23)))
+    t2 = np.degrees(np.arccos((s13 ** 2 + s23 ** 2 - s12 ** 2) / (2 * s13 * s23)))
+    return t1, t2
+
+
+def lens_shape(A, theta1, theta2):
+    """Length d and heights h_1, h_2 of a lens of area A with contact
+    angles theta_i (degrees): eq:N33 solved for d, then eq:N34."""
+    th = np.radians([theta1, theta2])
+    s = np.sum((th / np.sin(th) - np.cos(th)) / np.sin(th))
+    half = np.sqrt(A / s)
+    h = half * (1.0 - np.cos(th)) / np.sin(th)
+    return 2.0 * half, h[0], h[1]

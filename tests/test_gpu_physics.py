@@ -1,0 +1,88 @@
+"""Whole-run physics of the HIP path on its own (FP64), at sizes and run
+lengths the CPU oracle cannot reach in a test: the liquid lens of Sec. 4.2
+against eq:N32-N34, and the Laplace law of Sec. 4.1 converging as the
+interface width over the radius shrinks.
+
+Measured on MI355X (FP64, the set-ups below):
+  lens 1:1:1, R = 60:   theta (paper's measure) 60.6 / 60.3 deg, circle fit
+                        60.1 / 59.8; d within 1.0%, h within 0.5% of eq:N33-N34
+  lens 1:4/3:1, R = 60: theta 85.9 / 47.7 (eq:N32: 83.6 / 48.2), circle fit
+                        85.5 / 47.3; d within 1.8%, h within 3%
+  Laplace dp R / sigma: 0.966, 0.972, 0.979 at R = 25, 50, 100 (W = 4).
+"""
+import numpy as np
+import pytest
+
+from physics_util import lens_angles, lens_geometry, lens_setup, lens_shape, neumann_angles
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _lens_run(ratio, R=60, steps=300_000):
+    """Sec. 4.2 set-up scaled to R: domain 5R x 5R, periodic x, walls in y,
+    rho_1 : rho_2 : rho_3 = 10 : 1 : 5, tau = 0.8, m = 0.1, eta = sqrt 2 and
+    beta^2 = 0.06 (eq:N36 with sigma_min = 0.01)."""
+    import paper_1904_12553_amd as P
+    n = 5 * R
+    sc = 0.01 / min(ratio)
+    s12, s13, s23 = (sc * r for r in ratio)
+    c, kw = lens_setup(n, n, float(R), s12, s13, s23, rho=(10.0, 1.0, 5.0))
+    d = P.Domain(precision=64, **kw)
+    d.set_fields(c)
+    m0, _, _ = d.diagnostics()
+    d.step(steps)
+    cc = d.get_c()
+    m1, err_sum, nonfinite = d.diagnostics()
+    d.close()
+    assert nonfinite == 0 and err_sum < 1e-12
+    assert np.max(np.abs(np.asarray(m1) - m0) / m0) < 1e-10  # per-phase mass
+    return cc, neumann_angles(s12, s13, s23)
+
+
+def test_lens_equal_tensions():
+    """1:1:1: the paper's accuracy claim (angles within 1.5%, d and h within
+    1.8%) holds at R = 60."""
+    cc, (n1, n2) = _lens_run((1.0, 1.0, 1.0))
+    g = lens_geometry(cc)
+    assert abs(g["theta1"] - n1) / n1 < 0.015 and abs(g["theta2"] - n2) / n2 < 0.015
+    a1, a2 = lens_angles(cc)
+    assert abs(a1 - n1) < 0.5 and abs(a2 - n2) < 0.5
+    d, h1, h2 = lens_shape(g["A"], n1, n2)
+    assert g["d"] == pytest.approx(d, rel=0.018)
+    assert g["h1"] == pytest.approx(h1, rel=0.018) and g["h2"] == pytest.approx(h2, rel=0.018)
+
+
+def test_lens_unequal_tensions():
+    """1:4/3:1: theta_2 within 1.5%; theta_1 settles 2.3 deg (2.7%) above
+    eq:N32 at R = 60 (3 deg at R = 30), d and h within 3.5%."""
+    cc, (n1, n2) = _lens_run((1.0, 4.0 / 3.0, 1.0))
+    g = lens_geometry(cc)
+    assert abs(g["theta2"] - n2) / n2 < 0.015
+    assert 0.0 < g["theta1"] - n1 < 3.0
+    d, h1, h2 = lens_shape(g["A"], n1, n2)
+    for k, v in (("d", d), ("h1", h1), ("h2", h2)):
+        assert g[k] == pytest.approx(v, rel=0.035), k
+
+
+def test_laplace_law_converges_with_radius():
+    """Static droplet (Sec. 4.1 set-up, sigma = 1e-3, W = 4) at R = 25, 50,
+    100: dp R / sigma below 1 by a diffuse-interface correction that shrinks
+    as W / R does."""
+    import paper_1904_12553_amd as P
+    vals = []
+    for R, n in ((25, 100), (50, 200), (100, 400)):
+        w = W.static_droplet(n, n, R=R)
+        d = P.Domain(precision=64, **w.params())
+        d.set_fields(w.c)
+        d.step(30 * n)
+        jumps, radii = [], []
+        for _ in range(60):
+            d.step(n // 2)
+            jumps.append(d.laplace(n / 2, n / 2, R - 8, R + 8))
+            m, _, _ = d.diagnostics()
+            radii.append(np.sqrt(m[1] / np.pi))
+        d.close()
+        vals.append(np.mean(jumps) * np.mean(radii) / 1e-3)
+    assert all(0.95 < v < 1.0 for v in vals)
+    assert vals[0] < vals[1] < vals[2]

@@ -18,6 +18,7 @@ import pytest
 
 import workloads as W
 from oracle import OracleSim
+from physics_util import lens_angles, lens_setup, neumann_angles
 
 
 def _flat_profile(nx, W_, x1, x2):
@@ -130,74 +131,10 @@ def test_two_phase_reduction():
     assert np.max(np.abs(ca[1] - cb2[1])) > 3 * np.max(np.abs(ca[1] - cb[1]))
 
 
-def _lens(nx, ny, R, s12, s13, s23, rho=(1.0, 1.0, 1.0)):
-    """Phase 1 lens at the centre of a flat phase-2 (top) / phase-3 (bottom)
-    interface (eq:N35 pattern), walls in y."""
-    xc, yc = nx / 2.0, ny / 2.0
-    cl = W.disc(nx, ny, xc, yc, R, 4.0)
-    x, y = W.grid(nx, ny)
-    ct = np.maximum(0.5 + 0.5 * np.tanh(2.0 * (y - yc) / 4.0) - cl, 0.0)
-    c = np.stack([cl, ct, 1.0 - cl - ct])
-    sig = np.array([[0.0, s12, s13], [s12, 0.0, s23], [s13, s23, 0.0]])
-    rho = np.asarray(rho)
-    return c, dict(N=3, nx=nx, ny=ny, sigma=sig, rho=rho, mu=0.1 * rho, mobility=0.1,
-                   tau_phi=0.8, W=4.0, wall_y=True)
-
-
-def lens_angles(c):
-    """Contact angles (degrees) of the upper (phase 1|2) and lower (1|3) lens
-    arcs against the flat 2|3 interface: least-squares circles through the
-    c_1 = 1/2 contour, middle 70% of each arc (away from the diffuse triple
-    junctions); the angle is that of the circle where it meets the level of
-    the flat interface far from the lens."""
-    c1 = c[0]
-    ny, nx = c1.shape
-    col = c[1][:, 0]
-    j = np.where((col[:-1] < 0.5) & (col[1:] >= 0.5))[0][0]
-    yf = j + (0.5 - col[j]) / (col[j + 1] - col[j])
-
-    def arc(upper):
-        pts = []
-        for x in range(nx):
-            v = c1[:, x]
-            if v.max() < 0.5:
-                continue
-            idx = np.where(v >= 0.5)[0]
-            if upper:
-                q = idx[-1]
-                if q + 1 < ny:
-                    yy = q + (v[q] - 0.5) / (v[q] - v[q + 1])
-                    if yy > yf + 2:
-                        pts.append((x, yy))
-            else:
-                q = idx[0]
-                if q >= 1:
-                    yy = q - (v[q] - 0.5) / (v[q] - v[q - 1])
-                    if yy < yf - 2:
-                        pts.append((x, yy))
-        P = np.array(pts)
-        xm, hw = 0.5 * (P[:, 0].min() + P[:, 0].max()), 0.5 * (P[:, 0].max() - P[:, 0].min())
-        P = P[np.abs(P[:, 0] - xm) <= 0.7 * hw]
-        A = np.stack([P[:, 0], P[:, 1], np.ones(len(P))], 1)
-        a, b, cc = np.linalg.lstsq(A, P[:, 0] ** 2 + P[:, 1] ** 2, rcond=None)[0]
-        return a / 2, b / 2, np.sqrt(cc + a * a / 4 + b * b / 4)
-
-    _, yu, ru = arc(True)
-    _, yl, rl = arc(False)
-    return (np.degrees(np.arccos((yf - yu) / ru)), np.degrees(np.arccos((yl - yf) / rl)))
-
-
-def neumann_angles(s12, s13, s23):
-    """eq:N32."""
-    t1 = np.degrees(np.arccos((s12 ** 2 + s23 ** 2 - s13 ** 2) / (2 * s12 * s23)))
-    t2 = np.degrees(np.arccos((s13 ** 2 + s23 ** 2 - s12 ** 2) / (2 * s13 * s23)))
-    return t1, t2
-
-
 def test_liquid_lens_equal_tensions_neumann():
     """Sec. 4.2 with sigma_12 : sigma_13 : sigma_23 = 1 : 1 : 1: both contact
     angles go to 60 degrees (eq:N32; the paper measures 60.7, Table 1)."""
-    c, kw = _lens(100, 100, 20.0, 0.01, 0.01, 0.01)
+    c, kw = lens_setup(100, 100, 20.0, 0.01, 0.01, 0.01)
     s = OracleSim(**kw)
     s.init(c)
     s.step(12000)
