@@ -53,7 +53,12 @@ enum {
  *   wall_y          0: periodic in y; 1: halfway bounce-back walls below
  *                   row 0 and above row ny-1 (Sec. 4.2). x is periodic.
  *   precision       32 or 64: arithmetic and storage type of the state
- *   grad_scheme     0: isotropic central stencils of eq:N31a/b (only value)
+ *   grad_scheme     first derivatives of phi_i and C_i: 0 = isotropic
+ *                   central stencil of eq:N31a; 1 = isotropic mixed
+ *                   stencil of eq:N40 (Sec. 4.4) with its two-hop term
+ *                   -zeta(x + 2 c_i) (printed with a + sign, which would make
+ *                   it twice the gradient).  The Laplacian is eq:N31b in
+ *                   both.  Other values: NPLBM_EINVAL.
  *   sigma           N*N row-major pairwise tensions sigma_kl > 0, symmetric;
  *                   the diagonal is ignored
  *   rho, mu         N densities rho~_k > 0 and dynamic viscosities mu~_k > 0

@@ -8,7 +8,8 @@ streams by rolling, so that it shares neither structure nor helpers with the
 C oracle.
 
 Equations: eq:N1, eq:N12, eq:N14-N18, eq:N36 (setup and closure);
-eq:N31a/b (stencils); eq:24, eq:25, eq:N20_1, eq:N21_1, eq:N22_1, eq:N23
+eq:N31a/b (stencils), eq:N40 (mixed gradient, two-hop term read as
+negative); eq:24, eq:25, eq:N20_1, eq:N21_1, eq:N22_1, eq:N23
 (NS part); eq:N24-N28, eq:N30 (CH part).
 """
 from __future__ import annotations
@@ -23,8 +24,9 @@ CS2 = 1.0 / 3.0
 
 class LiteralSim:
     def __init__(self, N, nx, ny, sigma, rho, mu, mobility=0.1, tau_phi=0.8, W=4.0,
-                 wall_y=False, gx=0.0, gy=0.0, rho0=1.0):
+                 wall_y=False, gx=0.0, gy=0.0, rho0=1.0, grad_scheme=0):
         self.N, self.nx, self.ny = N, nx, ny
+        self.grad_scheme = int(grad_scheme)
         self.sig = np.asarray(sigma, float).reshape(N, N)
         self.rt = np.asarray(rho, float) * np.ones(N)
         self.mt = np.asarray(mu, float) * np.ones(N)
@@ -76,11 +78,23 @@ class LiteralSim:
         return pad[..., 2 + dy: 2 + dy + self.ny, :]
 
     def grad(self, f):                                           # eq:N31a
+        if self.grad_scheme == 1:
+            return self.grad_mixed(f)
         out = np.zeros((2,) + f.shape)
         for k in range(1, 9):
             d = self.shift(f, *C[k]) - self.shift(f, *(-C[k]))
             out[0] += WGT[k] * C[k, 0] * d / (2 * CS2)
             out[1] += WGT[k] * C[k, 1] * d / (2 * CS2)
+        return out
+
+    def grad_mixed(self, f):                                     # eq:N40
+        out = np.zeros((2,) + f.shape)
+        for k in range(1, 9):
+            cx, cy = C[k]
+            d = (-self.shift(f, 2 * cx, 2 * cy) + 5 * self.shift(f, cx, cy) - 3 * f
+                 - self.shift(f, -cx, -cy))
+            out[0] += WGT[k] * cx * d / (4 * CS2)
+            out[1] += WGT[k] * cy * d / (4 * CS2)
         return out
 
     def lap(self, f):                                            # eq:N31b

@@ -19,7 +19,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libnplbm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["step_kernel.hip", "aux_kernels.hip", "nplbm_host.cpp", "nplbm_api.cpp",
+SOURCES = ["step_kernel.hip", "step_kernel_mixed.hip", "aux_kernels.hip", "nplbm_host.cpp", "nplbm_api.cpp",
            "nplbm_server.cpp"]
 
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -58,6 +58,22 @@ __device__ __forceinline__ void grad9(const double *f, int x, int y, int nx, int
   gy = (4.0 * (n - s) + (ne + nw - se - sw)) / 12.0;
 }
 
+// eq:N40 (two-hop term read as negative) summed over the D2Q9 directions:
+// d/dx = [24 (E - W) - 4 (E2 - W2) + 6 (NE - NW + SE - SW)
+//         - (NE2 - NW2 + SE2 - SW2)] / 48, likewise d/dy.
+__device__ __forceinline__ void grad_mixed(const double *f, int x, int y, int nx, int ny,
+                                           bool wall, double &gx, double &gy) {
+  auto v = [&](int dx, int dy) { return f[nb(x, y, dx, dy, nx, ny, wall)]; };
+  gx = (24.0 * (v(1, 0) - v(-1, 0)) - 4.0 * (v(2, 0) - v(-2, 0)) +
+        6.0 * ((v(1, 1) - v(-1, 1)) + (v(1, -1) - v(-1, -1))) -
+        ((v(2, 2) - v(-2, 2)) + (v(2, -2) - v(-2, -2)))) /
+       48.0;
+  gy = (24.0 * (v(0, 1) - v(0, -1)) - 4.0 * (v(0, 2) - v(0, -2)) +
+        6.0 * ((v(1, 1) + v(-1, 1)) - (v(1, -1) + v(-1, -1))) -
+        ((v(2, 2) + v(-2, 2)) - (v(2, -2) + v(-2, -2)))) /
+       48.0;
+}
+
 // ---------------------------------------------------------------- init ----
 // phi_i from the volume fractions: eq:N12 inverted with rho_k = rho~_k c_k,
 // phi_i = (rho~_i c_i - rho~_N c_N - b_i) / a_i, which the host passes as
@@ -215,7 +231,10 @@ __global__ void k_macro_up(const DomDesc *dd, int M, int parity, const double *p
   double Fx = 0.0, Fy = 0.0, grx = 0.0, gry = 0.0;
   for (int i = 0; i < M; ++i) {
     double gx, gy;
-    grad9(phi + (int64_t)i * n, x, y, nx, ny, wall, gx, gy);
+    if (dd->grad == kGradMixed)
+      grad_mixed(phi + (int64_t)i * n, x, y, nx, ny, wall, gx, gy);
+    else
+      grad9(phi + (int64_t)i * n, x, y, nx, ny, wall, gx, gy);
     const double Ci = C[(int64_t)i * n + id];
     Fx += Ci * gx;
     Fy += Ci * gy;

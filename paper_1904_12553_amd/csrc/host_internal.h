@@ -48,7 +48,7 @@ int64_t plane_pad(size_t elem);
 // default padding of every row block of the row-interleaved layout
 constexpr size_t kRowPadBytes = 0;
 int64_t row_pad(size_t elem);
-int resident_step_blocks(int N, int precision);
+int resident_step_blocks(int N, int precision, int grad);
 void build_strips(int nx, int ny, int dom, const StepGeom &geom, std::vector<StripDesc> &out,
                   int target = 0);
 void xcd_order(std::vector<StripDesc> &s);

@@ -99,7 +99,8 @@ int derive(const nplbm_params *p, Derived &d) {
     return fail(NPLBM_EINVAL, "domain larger than 2^30 nodes");
   if (p->precision != 32 && p->precision != 64)
     return fail(NPLBM_EINVAL, "precision must be 32 or 64");
-  if (p->grad_scheme != 0) return fail(NPLBM_EINVAL, "grad_scheme must be 0");
+  if (p->grad_scheme != kGradCentral && p->grad_scheme != kGradMixed)
+    return fail(NPLBM_EINVAL, "grad_scheme must be 0 (eq:N31a) or 1 (eq:N40)");
   if (p->wall_y != 0 && p->wall_y != 1) return fail(NPLBM_EINVAL, "wall_y must be 0 or 1");
   if (!p->sigma || !p->rho || !p->mu || !p->mobility || !p->tau_phi)
     return fail(NPLBM_EINVAL, "a parameter array is NULL");
@@ -311,7 +312,7 @@ int64_t row_pad(size_t elem) {
 }
 
 // Workgroups the step kernel can keep resident on the device at once.
-int resident_step_blocks(int N, int precision) {
+int resident_step_blocks(int N, int precision, int grad) {
   static int cus = -1;
   if (cus < 0) {
     int dev = 0;
@@ -321,7 +322,7 @@ int resident_step_blocks(int N, int precision) {
     else
       cus = 0;
   }
-  const int per = step_blocks_per_cu(N, precision, step_geom(N, precision).bw);
+  const int per = step_blocks_per_cu(N, precision, grad, step_geom(N, precision, grad).bw);
   return cus > 0 && per > 0 ? cus * per : 0;
 }
 
@@ -332,7 +333,7 @@ int single_domain_target(const nplbm_params *p) {
     const int t = std::atoi(env);
     if (t > 0) return t;
   }
-  const int r = resident_step_blocks(p->N, p->precision);
+  const int r = resident_step_blocks(p->N, p->precision, p->grad_scheme);
   return r > 0 ? r : 2048;
 }
 
@@ -384,25 +385,25 @@ Layout plan_layout(const nplbm_params *p) {
   return L;
 }
 
-// Strip geometry of the step kernel for a precision.  Interior strip widths
-// are multiples of 64 bytes of state, so no 64-byte memory sector is written
-// by two workgroups.
+// Strip geometry of the step kernel for a precision and gradient scheme.
 // Interior widths are multiples of one 128-byte cache line of state values
 // (32 floats or 16 doubles), so no line is written by two workgroups; rows
-// of 256 threads for FP32 and 64 for FP64 measured fastest on gfx950.
-StepGeom step_geom(int N, int precision) {
+// of 256 threads for FP32 and 64 for FP64 measured fastest on gfx950.  The
+// halo is 2 columns for the central gradients and 3 for the two-hop ones.
+StepGeom step_geom(int N, int precision, int grad) {
   StepGeom g;
+  g.halo = grad == kGradMixed ? 3 : 2;
   const int unit = precision == 64 ? 16 : 32;
   g.bw = precision == 64 ? 64 : 256;
   if (const char *e = std::getenv("NPLBM_BW")) {
     const int b = std::atoi(e);
     g.bw = (b == 128 || b == 256) ? b : 64;
   }
-  g.bw = std::min(g.bw, step_max_bw(N, precision));
-  g.tx = ((g.bw - 4) / unit) * unit;
+  g.bw = std::min(g.bw, step_max_bw(N, precision, grad));
+  g.tx = ((g.bw - 2 * g.halo) / unit) * unit;
   if (const char *e = std::getenv("NPLBM_TX")) g.tx = std::atoi(e);
   if (g.tx < 8) g.tx = 8;
-  if (g.tx > g.bw - 4) g.tx = g.bw - 4;
+  if (g.tx > g.bw - 2 * g.halo) g.tx = g.bw - 2 * g.halo;
   g.unit = unit;
   return g;
 }

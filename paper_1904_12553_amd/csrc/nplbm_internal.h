@@ -11,18 +11,24 @@ constexpr int kMaxN = 8;          // phases
 constexpr int kMaxM = kMaxN - 1;  // order parameters
 constexpr int kRows = 2;  // rows per marching iteration (one or more waves per row)
 // Row width of a step workgroup in threads (a multiple of the 64-lane wave):
-// each row covers the strip's interior columns plus a 2-column halo on each
-// side; lanes beyond that stay idle.
+// each row covers the strip's interior columns plus a halo of `halo` columns
+// on each side (2 for the central gradients of eq:N31a, 3 for the two-hop
+// gradients of eq:N40); lanes beyond that stay idle.
 struct StepGeom {
   int bw;    // threads per row (64, 128 or 256)
-  int tx;    // maximum interior columns per strip (<= bw - 4)
+  int tx;    // maximum interior columns per strip (<= bw - 2 halo)
   int unit;  // strip widths are multiples of this many columns (one cache line)
+  int halo;  // halo columns on each side
 };
-// Geometry used for N phases at a precision (32 / 64); NPLBM_BW and
-// NPLBM_TX override.
-StepGeom step_geom(int N, int precision);
-// widest row width the step kernel is built with for (N, precision)
-int step_max_bw(int N, int precision);
+// Gradient schemes: central isotropic (eq:N31a) or the isotropic mixed scheme
+// of eq:N40 (sign of its two-hop term read as negative).
+constexpr int kGradCentral = 0;
+constexpr int kGradMixed = 1;
+// Geometry used for N phases at a precision (32 / 64) and gradient scheme;
+// NPLBM_BW and NPLBM_TX override.
+StepGeom step_geom(int N, int precision, int grad);
+// widest row width the step kernel is built with for (N, precision, grad)
+int step_max_bw(int N, int precision, int grad);
 
 // Per-domain constants, folded on the host from the paper's closure so that
 // every per-node quantity is an affine map or a short dot product:
@@ -67,7 +73,7 @@ struct DomDesc {
   int32_t N;
   int32_t parity0;   // buffer holding the current state at substep 0
   int32_t steps_left;  // substeps >= steps_left do nothing
-  int32_t pad_;
+  int32_t grad;        // gradient scheme (kGradCentral / kGradMixed)
   Consts<double> cd;
   Consts<float> cf;
 };
@@ -91,10 +97,17 @@ struct StepArgs {
 };
 
 // Launchers (defined in the .hip files).  All are asynchronous on `st`.
-hipError_t launch_step(int N, int precision, int bw, const StepArgs &a, int nblocks,
-                       hipStream_t st);
+hipError_t launch_step(int N, int precision, int grad, int bw, const StepArgs &a,
+                       int nblocks, hipStream_t st);
 // resident step-kernel workgroups per compute unit (0 if unknown)
-int step_blocks_per_cu(int N, int precision, int bw);
+int step_blocks_per_cu(int N, int precision, int grad, int bw);
+// the same for one gradient scheme (one translation unit each)
+hipError_t launch_step_central(int N, int precision, int bw, const StepArgs &a, int nblocks,
+                               hipStream_t st);
+hipError_t launch_step_mixed(int N, int precision, int bw, const StepArgs &a, int nblocks,
+                             hipStream_t st);
+int step_blocks_per_cu_central(int N, int precision, int bw);
+int step_blocks_per_cu_mixed(int N, int precision, int bw);
 
 // Initialisation: phi (double, (N-1) planes of nx*ny) is computed from c,
 // then C from phi, then h^eq / g^eq written in pull layout.

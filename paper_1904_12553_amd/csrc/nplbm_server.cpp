@@ -71,7 +71,7 @@ struct nplbm_server {
   StripDesc *strips_dev = nullptr;
   size_t strips_cap = 0;
   struct Group {
-    int N, precision;
+    int N, precision, grad;
     size_t off, count;
   };
   std::vector<Group> groups;
@@ -129,6 +129,7 @@ int admit(nplbm_server *s, Req *r) {
   D.N = r->p.N;
   D.parity0 = 0;
   D.steps_left = INT_MAX;
+  D.grad = r->p.grad_scheme;
   D.cd = r->d.cd;
   D.cf = r->d.cf;
   const size_t n = (size_t)r->p.nx * r->p.ny;
@@ -158,8 +159,8 @@ int admit(nplbm_server *s, Req *r) {
   return NPLBM_OK;
 }
 
-// Rebuild the packed strip tables (one per (N, precision) group) and
-// recapture the quantum graph.
+// Rebuild the packed strip tables (one per (N, precision, gradient scheme)
+// group) and recapture the quantum graph.
 int rebuild(nplbm_server *s) {
   if (s->graph) {
     (void)hipGraphExecDestroy(s->graph);
@@ -167,19 +168,20 @@ int rebuild(nplbm_server *s) {
   }
   s->groups.clear();
   std::vector<StripDesc> all;
-  for (int prec : {32, 64})
-    for (int N = 2; N <= kMaxN; ++N) {
-      std::vector<StripDesc> g;
-      for (int slot = 0; slot < s->max_slots; ++slot) {
-        Req *r = s->slots[slot];
-        if (!r || r->p.N != N || r->p.precision != prec) continue;
-        build_strips(r->p.nx, r->p.ny, slot, step_geom(N, prec), g);
+  for (int grad : {kGradCentral, kGradMixed})
+    for (int prec : {32, 64})
+      for (int N = 2; N <= kMaxN; ++N) {
+        std::vector<StripDesc> g;
+        for (int slot = 0; slot < s->max_slots; ++slot) {
+          Req *r = s->slots[slot];
+          if (!r || r->p.N != N || r->p.precision != prec || r->p.grad_scheme != grad) continue;
+          build_strips(r->p.nx, r->p.ny, slot, step_geom(N, prec, grad), g);
+        }
+        if (g.empty()) continue;
+        xcd_order(g);
+        s->groups.push_back({N, prec, grad, all.size(), g.size()});
+        all.insert(all.end(), g.begin(), g.end());
       }
-      if (g.empty()) continue;
-      xcd_order(g);
-      s->groups.push_back({N, prec, all.size(), g.size()});
-      all.insert(all.end(), g.begin(), g.end());
-    }
   s->dirty = false;
   if (all.empty()) return NPLBM_OK;
   if (all.size() > s->strips_cap) {
@@ -207,7 +209,7 @@ int rebuild(nplbm_server *s) {
       a.strips = s->strips_dev + gr.off;
       a.doms = s->descs_dev;
       a.substep = q;
-      le = launch_step(gr.N, gr.precision, step_geom(gr.N, gr.precision).bw, a,
+      le = launch_step(gr.N, gr.precision, gr.grad, step_geom(gr.N, gr.precision, gr.grad).bw, a,
                        (int)gr.count, s->stream);
       if (le != hipSuccess) break;
     }

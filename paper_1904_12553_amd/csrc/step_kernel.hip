@@ -2,25 +2,33 @@
 // (arXiv:1904.12553, Sec. 3) for gfx950.
 //
 // One launch advances every node of every listed domain by one time step.
-// Work decomposition: a workgroup owns a strip of kTX interior columns and
-// [y0, y1) rows and marches along y, two rows per iteration (one wave per
-// row, 64 lanes = kTX interior columns + a 2-column halo on each side).
+// Work decomposition: a workgroup owns a strip of interior columns and
+// [y0, y1) rows and marches along y, two rows per iteration (one row of
+// kBW lanes per march row: the interior columns plus a halo on each side).
 // Per iteration, with march index m counted from the strip start:
 //
-//   stage A (rows m, m+1 ahead by 2): pull the 9(N-1) CH populations from
-//            the neighbours (streaming fused into the load), phi_i = sum_k h
-//            (eq:N28) -> LDS ring of 8 rows;
+//   stage A (rows m, m+1): pull the 9(N-1) CH populations from the
+//            neighbours (streaming fused into the load), phi_i = sum_k h
+//            (eq:N28) -> LDS ring;
 //   stage B (1 row behind A): Laplacian of eq:N31b on the LDS ring, closure
-//            eq:N18 and eq:N17 -> chemical potentials C_i -> LDS ring of 4;
-//   stage C (2 rows behind A): gradients of phi_i and C_i (eq:N31a) from the
-//            rings, forces F (Sec. 3.1) and J~, pull the 8 moving NS
-//            populations, u (eq:N22_1), p (eq:N23), NS collision (eq:24 with
-//            eq:25 and eq:N20_1) and CH collisions (eq:N24 with eq:N25-N27)
-//            using the CH populations this thread pulled one iteration
-//            earlier (kept in registers), then store.
+//            eq:N18 and eq:N17 -> chemical potentials C_i -> LDS ring;
+//   stage C (kLag rows behind A): gradients of phi_i and C_i from the rings,
+//            forces F (Sec. 3.1) and J~, pull the 8 moving NS populations,
+//            u (eq:N22_1), p (eq:N23), NS collision (eq:24 with eq:25 and
+//            eq:N20_1) and CH collisions (eq:N24 with eq:N25-N27) using the
+//            CH populations this thread pulled kLag rows earlier (kept in
+//            registers), then store.
+//
+// Two gradient schemes are built (template parameter kGS):
+//   - central (eq:N31a): one-hop stencils; 2-column halo, C needed one row
+//     ahead of the collision, so kLag = 2;
+//   - mixed (eq:N40 with its two-hop term read as negative): two-hop
+//     stencils; 3-column halo, C needed two rows ahead, phi three, and the
+//     lag must be even (a row is pulled and collided by the same wave), so
+//     kLag = 4 and a third register set holds the pulls in between.
 //
 // So every population is read from HBM once and written once per step; the
-// only re-reads are the 2-column x-halo and a 4-row ramp at the strip start,
+// only re-reads are the x-halo and a short row ramp at the strip start,
 // both L2/MALL-resident.  Rest populations are dropped or stored as
 // deviations from their rest-state value:
 //   - g_0 never feeds u, p or phi (c_0 = 0 and eq:N23 sums k != 0), so only
@@ -104,9 +112,30 @@ struct PulledNS {
   Real pu[2];  // stored u of the previous step
 };
 
-template <int N, typename Real, int kBW>
+// Ring sizes and march offsets of each gradient scheme: phi ring, C ring,
+// halo columns, rows pulled before the strip start (ramp), and rows between
+// the pull and the collision of a node (lag).
+template <int kGS>
+struct Scheme;
+template <>
+struct Scheme<0> {
+  static constexpr int kPR = 8, kCR = 4, kHalo = 2, kRamp = 2, kLag = 2;
+};
+template <>
+struct Scheme<1> {
+  static constexpr int kPR = 10, kCR = 8, kHalo = 3, kRamp = 4, kLag = 4;
+};
+// slot of march index m (m >= -16 R) in a ring of R rows
+template <int R>
+__device__ __forceinline__ int ring(int m) {
+  return (m + 16 * R) % R;
+}
+
+template <int N, typename Real, int kBW, int kGS>
 __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a) {
   constexpr int M = N - 1;
+  using S = Scheme<kGS>;
+  constexpr int kPR = S::kPR, kCR = S::kCR, kHalo = S::kHalo;
   typedef const NPL_GLOBAL Real *GIn;
   typedef NPL_GLOBAL Real *GOut;
   const NPL_CONST StripDesc *sp = (const NPL_CONST StripDesc *)a.strips + blockIdx.x;
@@ -134,14 +163,14 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   const size_t psh = (size_t)D->ps[0], psg = (size_t)D->ps[1], psp = (size_t)D->ps[2];
   const size_t rsh = (size_t)D->rs[0], rsg = (size_t)D->rs[1], rsp = (size_t)D->rs[2];
 
-  __shared__ Real sphi[8][M][kBW];
-  __shared__ Real sC[4][M][kBW];
+  __shared__ Real sphi[kPR][M][kBW];
+  __shared__ Real sC[kCR][M][kBW];
 
   const int lane = threadIdx.x & (kBW - 1);
   // the row handled by this wave (uniform; said explicitly so every row,
   // bounce-back and plane decision stays in scalar registers)
   const int ry = __builtin_amdgcn_readfirstlane(threadIdx.x / kBW);
-  const int xl = sd.x0 - 2 + lane;
+  const int xl = sd.x0 - kHalo + lane;
   int xc = xl % nx;
   if (xc < 0) xc += nx;
   constexpr uint32_t SZ = sizeof(Real);
@@ -149,7 +178,7 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   const uint32_t xw = (xc == 0 ? (uint32_t)(nx - 1) : (uint32_t)xc - 1) * SZ;  // x - 1
   const uint32_t xe = (xc == nx - 1 ? 0u : (uint32_t)xc + 1) * SZ;             // x + 1
   const int ncol = sd.x1 - sd.x0;  // interior columns of this strip
-  const bool interior = lane >= 2 && lane < ncol + 2;
+  const bool interior = lane >= kHalo && lane < ncol + kHalo;
   const int H = sd.y1 - sd.y0;
   const int dir = sd.dir;
 
@@ -234,21 +263,27 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
 
   // ---- stage A: phi of march index mA -> LDS ----
   auto stageA = [&](int mA, const Pulled<M, Real> &cur) {
-    const int slot = (mA + 8) & 7;
+    const int slot = ring<kPR>(mA);
 #pragma unroll
     for (int i = 0; i < M; ++i) sphi[slot][i][lane] = cur.hi[i] + lo_sum(cur.h[i]);  // eq:N28
   };
 
   // ---- stage B: chemical potentials for march index mB -> LDS ----
+  // C is needed on the interior columns and one (central) or two (mixed)
+  // columns either side.  Next to a wall, C of a ghost row is the mirror of
+  // C inside: the central scheme reads it from the row it mirrors (C(-1) =
+  // C(0)); the mixed scheme needs two ghost rows, C(-2) = C(1) being ahead
+  // of the march, and evaluates them on the mirrored phi rows the ring
+  // holds, which gives the same values (the stencil is mirror-symmetric).
   auto stageB = [&](int mB) {
-    if (lane < 1 || lane > ncol + 2) return;
+    if (lane < 1 || lane > ncol + 2 * kHalo - 2) return;
     int me = mB;
-    if (wall) {
+    if (kGS == 0 && wall) {
       const int r = row_of(mB);
       if (r < 0) me = mB + dir;          // ghost below row 0: C(-1) = C(0)
       else if (r >= ny) me = mB - dir;   // ghost above row ny-1
     }
-    const int s0 = (me + 8) & 7, s1 = (me + 9) & 7, s2 = (me + 7) & 7;
+    const int s0 = ring<kPR>(me), s1 = ring<kPR>(me + 1), s2 = ring<kPR>(me - 1);
     Real phi[M], lap[M];
 #pragma unroll
     for (int i = 0; i < M; ++i) {
@@ -270,7 +305,7 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
       for (int i = 0; i < M; ++i) ck += K.cA[k][i] * phi[i];
       wv[k] = ck * (Real(1) - ck) * (Real(1) - Real(2) * ck);
     }
-    const int sc = (mB + 4) & 3;
+    const int sc = ring<kCR>(mB);
 #pragma unroll
     for (int i = 0; i < M; ++i) {
       Real Ci = Real(0);
@@ -286,29 +321,59 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   auto stageC = [&](int mC, const Pulled<M, Real> &P, const PulledNS<Real> &Q) {
     if (!interior || mC < 0 || mC >= H) return;
     const int yp = row_of(mC);
-    const int p0 = (mC + 8) & 7, pN = (mC + dir + 8) & 7, pS = (mC - dir + 8) & 7;
-    const int q0 = (mC + 4) & 3, qN = (mC + dir + 4) & 3, qS = (mC - dir + 4) & 3;
+    const int p0 = ring<kPR>(mC), pN = ring<kPR>(mC + dir), pS = ring<kPR>(mC - dir);
+    const int q0 = ring<kCR>(mC), qN = ring<kCR>(mC + dir), qS = ring<kCR>(mC - dir);
     Real phi[M], Cv[M], gpx[M], gpy[M], gCx[M], gCy[M];
-    // eq:N31a on D2Q9: d/dx = [4 (E - W) + (NE - NW + SE - SW)] / 12
+    if constexpr (kGS == 0) {
+      // eq:N31a on D2Q9: d/dx = [4 (E - W) + (NE - NW + SE - SW)] / 12
+      auto grad = [&](const Real (*f)[M][kBW], int r0, int rN, int rS, int i, Real &gx,
+                      Real &gy) {
+        const Real e = f[r0][i][lane + 1], w = f[r0][i][lane - 1];
+        const Real n = f[rN][i][lane], s = f[rS][i][lane];
+        const Real ne = f[rN][i][lane + 1], nw = f[rN][i][lane - 1];
+        const Real se = f[rS][i][lane + 1], sw = f[rS][i][lane - 1];
+        gx = (Real(4) * (e - w) + ((ne - nw) + (se - sw))) * (Real(1) / Real(12));
+        gy = (Real(4) * (n - s) + ((ne + nw) - (se + sw))) * (Real(1) / Real(12));
+      };
 #pragma unroll
-    for (int i = 0; i < M; ++i) {
-      phi[i] = sphi[p0][i][lane];
-      {
-        const Real e = sphi[p0][i][lane + 1], w = sphi[p0][i][lane - 1];
-        const Real n = sphi[pN][i][lane], s = sphi[pS][i][lane];
-        const Real ne = sphi[pN][i][lane + 1], nw = sphi[pN][i][lane - 1];
-        const Real se = sphi[pS][i][lane + 1], sw = sphi[pS][i][lane - 1];
-        gpx[i] = (Real(4) * (e - w) + ((ne - nw) + (se - sw))) * (Real(1) / Real(12));
-        gpy[i] = (Real(4) * (n - s) + ((ne + nw) - (se + sw))) * (Real(1) / Real(12));
+      for (int i = 0; i < M; ++i) {
+        phi[i] = sphi[p0][i][lane];
+        Cv[i] = sC[q0][i][lane];
+        grad(sphi, p0, pN, pS, i, gpx[i], gpy[i]);
+        grad(sC, q0, qN, qS, i, gCx[i], gCy[i]);
       }
-      Cv[i] = sC[q0][i][lane];
-      {
-        const Real e = sC[q0][i][lane + 1], w = sC[q0][i][lane - 1];
-        const Real n = sC[qN][i][lane], s = sC[qS][i][lane];
-        const Real ne = sC[qN][i][lane + 1], nw = sC[qN][i][lane - 1];
-        const Real se = sC[qS][i][lane + 1], sw = sC[qS][i][lane - 1];
-        gCx[i] = (Real(4) * (e - w) + ((ne - nw) + (se - sw))) * (Real(1) / Real(12));
-        gCy[i] = (Real(4) * (n - s) + ((ne + nw) - (se + sw))) * (Real(1) / Real(12));
+    } else {
+      // eq:N40 summed over the D2Q9 directions.  Per direction c the
+      // difference is -z(x+2c) + 5 z(x+c) - 3 z(x) - z(x-c); with w_c, c_x
+      // and 1/(4 c_s^2) the z(x) terms cancel and opposite directions pair:
+      //   d/dx = [24 (E - W) - 4 (E2 - W2) + 6 (NE - NW + SE - SW)
+      //           - (NE2 - NW2 + SE2 - SW2)] / 48
+      // (E2 = z(x+2, y), NE2 = z(x+2, y+2), ...), and likewise d/dy.
+      const int pN2 = ring<kPR>(mC + 2 * dir), pS2 = ring<kPR>(mC - 2 * dir);
+      const int qN2 = ring<kCR>(mC + 2 * dir), qS2 = ring<kCR>(mC - 2 * dir);
+      auto grad = [&](const Real (*f)[M][kBW], int r0, int rN, int rS, int rN2, int rS2, int i,
+                      Real &gx, Real &gy) {
+        const Real e = f[r0][i][lane + 1], w = f[r0][i][lane - 1];
+        const Real e2 = f[r0][i][lane + 2], w2 = f[r0][i][lane - 2];
+        const Real n = f[rN][i][lane], s = f[rS][i][lane];
+        const Real n2 = f[rN2][i][lane], s2 = f[rS2][i][lane];
+        const Real ne = f[rN][i][lane + 1], nw = f[rN][i][lane - 1];
+        const Real se = f[rS][i][lane + 1], sw = f[rS][i][lane - 1];
+        const Real ne2 = f[rN2][i][lane + 2], nw2 = f[rN2][i][lane - 2];
+        const Real se2 = f[rS2][i][lane + 2], sw2 = f[rS2][i][lane - 2];
+        gx = (Real(24) * (e - w) - Real(4) * (e2 - w2) + Real(6) * ((ne - nw) + (se - sw)) -
+              ((ne2 - nw2) + (se2 - sw2))) *
+             (Real(1) / Real(48));
+        gy = (Real(24) * (n - s) - Real(4) * (n2 - s2) + Real(6) * ((ne + nw) - (se + sw)) -
+              ((ne2 + nw2) - (se2 + sw2))) *
+             (Real(1) / Real(48));
+      };
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        phi[i] = sphi[p0][i][lane];
+        Cv[i] = sC[q0][i][lane];
+        grad(sphi, p0, pN, pS, pN2, pS2, i, gpx[i], gpy[i]);
+        grad(sC, q0, qN, qS, qN2, qS2, i, gCx[i], gCy[i]);
       }
     }
     // density, relaxation, forces
@@ -410,32 +475,75 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
     st(prow + (size_t)(M + 1) * psp, xcu, uy);
   };
 
-  // March over iterations j (march index mA = 2j - 2 + row).  Each does
-  //   phi(mA) -> LDS | barrier | NS pulls of mA - 2 | C(mA - 1) | barrier |
-  //   collide mA - 2
-  // with the CH pulls of row mA held in registers until their collision two
-  // iterations later.  FP32 up to N = 5 has the registers to pipeline one
-  // more set: the CH pulls of mA + 2 are issued right after the first
-  // barrier, so they are in flight during stages B and C (three sets rotate:
-  // cur = mA, next = mA + 2, held = mA - 2).  FP64 and larger N keep two
-  // sets and their occupancy; three would halve it or spill.
-  const int J = (H + 5) / 2;
+  // March over iterations j (march index mA = 2j - kRamp + row).  Each does
+  //   phi(mA) -> LDS | barrier | NS pulls of mA - kLag | C(mA - 1) |
+  //   barrier | collide mA - kLag
+  // with the CH pulls of row mA held in registers until their collision
+  // kLag / 2 iterations later.
+  //  - central, FP32, N <= 5: the registers allow pipelining one more set:
+  //    the CH pulls of mA + 2 are issued right after the first barrier, so
+  //    they are in flight during stages B and C (three sets rotate: cur =
+  //    mA, next = mA + 2, held = mA - 2);
+  //  - central otherwise: two sets (cur, held = mA - 2); three would halve
+  //    the occupancy or spill;
+  //  - mixed, N <= 4: three sets (cur, mA - 2, mA - 4);
+  //  - mixed, N >= 5: three sets would spill or leave one wave per SIMD, so
+  //    the collision row's CH populations are pulled a second time (from
+  //    L2 / MALL, 2 iterations after the first pull) and one set suffices.
+  //    Measured on the 2048^2 N = 5 workload: 45% of the HBM roofline in
+  //    FP32 against 37% with three sets (the re-read costs the central
+  //    scheme 13 points, so it is used only here).
+  constexpr int kRamp = S::kRamp, kLag = S::kLag;
+  constexpr bool kRepull = kGS == 1 && N >= 5;
+  const int J = (H + kRamp + kLag + 1) / 2;
   PulledNS<Real> ns;
-  constexpr bool kPipeline = sizeof(Real) == 4 && N <= 5;
-  if constexpr (kPipeline) {
+  constexpr bool kPipeline = kGS == 0 && sizeof(Real) == 4 && N <= 5;
+  if constexpr (kRepull) {
+    // one register set: the CH populations of the collision row are loaded
+    // again (from L2 / MALL) right after the first barrier
+    Pulled<M, Real> buf;
+    for (int j = 0; j < J; ++j) {
+      const int mA = 2 * j - kRamp + ry;
+      pull_ch(mA, buf);
+      stageA(mA, buf);
+      __syncthreads();
+      pull_ns(mA - kLag, ns);
+      pull_ch(mA - kLag, buf);
+      stageB(mA - 1);
+      __syncthreads();
+      stageC(mA - kLag, buf, ns);
+    }
+  } else if constexpr (kGS == 1) {
+    Pulled<M, Real> bufA, bufB, bufC;
+    auto iteration = [&](int j, Pulled<M, Real> &cur, const Pulled<M, Real> &held) {
+      const int mA = 2 * j - kRamp + ry;
+      pull_ch(mA, cur);
+      stageA(mA, cur);
+      __syncthreads();
+      pull_ns(mA - kLag, ns);
+      stageB(mA - 1);
+      __syncthreads();
+      stageC(mA - kLag, held, ns);
+    };
+    for (int j = 0; j < J; j += 3) {  // j is uniform over the block
+      iteration(j, bufA, bufB);       // bufB holds the pulls of iteration j - 2
+      if (j + 1 < J) iteration(j + 1, bufB, bufC);
+      if (j + 2 < J) iteration(j + 2, bufC, bufA);
+    }
+  } else if constexpr (kPipeline) {
     Pulled<M, Real> bufA, bufB, bufC;
     auto iteration = [&](int j, const Pulled<M, Real> &cur, Pulled<M, Real> &next,
                          const Pulled<M, Real> &held) {
-      const int mA = 2 * j - 2 + ry;
+      const int mA = 2 * j - kRamp + ry;
       stageA(mA, cur);
       __syncthreads();
-      pull_ns(mA - 2, ns);
+      pull_ns(mA - kLag, ns);
       pull_ch(mA + 2, next);
       stageB(mA - 1);
       __syncthreads();
-      stageC(mA - 2, held, ns);
+      stageC(mA - kLag, held, ns);
     };
-    pull_ch(ry - 2, bufA);
+    pull_ch(ry - kRamp, bufA);
     for (int j = 0; j < J; j += 3) {  // j is uniform over the block
       iteration(j, bufA, bufB, bufC);
       if (j + 1 < J) iteration(j + 1, bufB, bufC, bufA);
@@ -444,14 +552,14 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   } else {
     Pulled<M, Real> bufA, bufB;  // pulled for mA (cur) and for mA - 2 (held)
     auto iteration = [&](int j, Pulled<M, Real> &cur, const Pulled<M, Real> &held) {
-      const int mA = 2 * j - 2 + ry;
+      const int mA = 2 * j - kRamp + ry;
       pull_ch(mA, cur);
       stageA(mA, cur);
       __syncthreads();
-      pull_ns(mA - 2, ns);
+      pull_ns(mA - kLag, ns);
       stageB(mA - 1);
       __syncthreads();
-      stageC(mA - 2, held, ns);
+      stageC(mA - kLag, held, ns);
     };
     for (int j = 0; j < J; j += 2) {  // j is uniform over the block
       iteration(j, bufA, bufB);
@@ -460,27 +568,48 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   }
 }
 
-// LDS of one workgroup: rings of 8 phi rows and 4 C rows of (N-1) x BW values
-constexpr int lds_bytes(int N, int bytes, int bw) { return 12 * (N - 1) * bw * bytes; }
-// the widest row a (N, precision) pair is built for: at most 64 KiB of LDS
-constexpr int max_bw(int N, int bytes) {
-  return lds_bytes(N, bytes, 256) <= 65536 ? 256 : (lds_bytes(N, bytes, 128) <= 65536 ? 128 : 64);
+// This translation unit instantiates the kernel for one gradient scheme,
+// NPL_GS (0 central, 1 mixed; step_kernel_mixed.hip builds the latter), so
+// the two sets of instantiations compile in parallel.
+#ifndef NPL_GS
+#define NPL_GS 0
+#endif
+
+// LDS of one workgroup: the phi and C rings of (N-1) x BW values
+constexpr int lds_bytes(int N, int bytes, int bw, int gs) {
+  return (gs ? Scheme<1>::kPR + Scheme<1>::kCR : Scheme<0>::kPR + Scheme<0>::kCR) * (N - 1) *
+         bw * bytes;
+}
+// LDS budget of a workgroup: 64 KiB for the central scheme; 80 KiB for the
+// mixed one (gfx950 has 160 KiB per CU, so two such workgroups still fit)
+constexpr int lds_budget(int gs) { return gs ? 80 * 1024 : 64 * 1024; }
+// the widest row a (N, precision, scheme) is built for
+constexpr int max_bw(int N, int bytes, int gs) {
+  return lds_bytes(N, bytes, 256, gs) <= lds_budget(gs)
+             ? 256
+             : (lds_bytes(N, bytes, 128, gs) <= lds_budget(gs) ? 128 : 64);
 }
 
-int step_max_bw(int N, int precision) {
-  return max_bw(N, precision == 64 ? 8 : 4);
+#if NPL_GS == 0
+int step_max_bw(int N, int precision, int grad) {
+  return max_bw(N, precision == 64 ? 8 : 4, grad == kGradMixed ? 1 : 0);
 }
+#endif
+
+namespace {
 
 template <int N, int BW>
-static hipError_t launch_nb(int precision, const StepArgs &a, int nblocks, hipStream_t st) {
+hipError_t launch_nb(int precision, const StepArgs &a, int nblocks, hipStream_t st) {
   if (precision == 64) {
-    if constexpr (BW <= max_bw(N, 8))
-      hipLaunchKernelGGL((k_step<N, double, BW>), dim3(nblocks), dim3(BW * kRows), 0, st, a);
+    if constexpr (BW <= max_bw(N, 8, NPL_GS))
+      hipLaunchKernelGGL((k_step<N, double, BW, NPL_GS>), dim3(nblocks), dim3(BW * kRows), 0,
+                         st, a);
     else
       return hipErrorInvalidValue;
   } else {
-    if constexpr (BW <= max_bw(N, 4))
-      hipLaunchKernelGGL((k_step<N, float, BW>), dim3(nblocks), dim3(BW * kRows), 0, st, a);
+    if constexpr (BW <= max_bw(N, 4, NPL_GS))
+      hipLaunchKernelGGL((k_step<N, float, BW, NPL_GS>), dim3(nblocks), dim3(BW * kRows), 0,
+                         st, a);
     else
       return hipErrorInvalidValue;
   }
@@ -488,34 +617,43 @@ static hipError_t launch_nb(int precision, const StepArgs &a, int nblocks, hipSt
 }
 
 template <int N>
-static hipError_t launch_n(int precision, int bw, const StepArgs &a, int nblocks,
-                           hipStream_t st) {
+hipError_t launch_n(int precision, int bw, const StepArgs &a, int nblocks, hipStream_t st) {
   return bw == 256   ? launch_nb<N, 256>(precision, a, nblocks, st)
          : bw == 128 ? launch_nb<N, 128>(precision, a, nblocks, st)
                      : launch_nb<N, 64>(precision, a, nblocks, st);
 }
 
 template <int N, int BW>
-static int occ_nb(int precision) {
+int occ_nb(int precision) {
   int nb = 0;
   hipError_t e = hipErrorInvalidValue;
   if (precision == 64) {
-    if constexpr (BW <= max_bw(N, 8))
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<N, double, BW>, BW * kRows, 0);
+    if constexpr (BW <= max_bw(N, 8, NPL_GS))
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<N, double, BW, NPL_GS>,
+                                                       BW * kRows, 0);
   } else {
-    if constexpr (BW <= max_bw(N, 4))
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<N, float, BW>, BW * kRows, 0);
+    if constexpr (BW <= max_bw(N, 4, NPL_GS))
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<N, float, BW, NPL_GS>,
+                                                       BW * kRows, 0);
   }
   return e == hipSuccess ? nb : 0;
 }
 
 template <int N>
-static int occ_n(int precision, int bw) {
+int occ_n(int precision, int bw) {
   return bw == 256 ? occ_nb<N, 256>(precision)
                    : (bw == 128 ? occ_nb<N, 128>(precision) : occ_nb<N, 64>(precision));
 }
 
-int step_blocks_per_cu(int N, int precision, int bw) {
+}  // namespace
+
+#if NPL_GS == 0
+#define NPL_SCHEME_FN(name) name##_central
+#else
+#define NPL_SCHEME_FN(name) name##_mixed
+#endif
+
+int NPL_SCHEME_FN(step_blocks_per_cu)(int N, int precision, int bw) {
   switch (N) {
     case 2: return occ_n<2>(precision, bw);
     case 3: return occ_n<3>(precision, bw);
@@ -528,8 +666,8 @@ int step_blocks_per_cu(int N, int precision, int bw) {
   }
 }
 
-hipError_t launch_step(int N, int precision, int bw, const StepArgs &a, int nblocks,
-                       hipStream_t st) {
+hipError_t NPL_SCHEME_FN(launch_step)(int N, int precision, int bw, const StepArgs &a,
+                                      int nblocks, hipStream_t st) {
   if (nblocks <= 0) return hipSuccess;
   switch (N) {
     case 2: return launch_n<2>(precision, bw, a, nblocks, st);
@@ -542,5 +680,18 @@ hipError_t launch_step(int N, int precision, int bw, const StepArgs &a, int nblo
     default: return hipErrorInvalidValue;
   }
 }
+
+#if NPL_GS == 0
+int step_blocks_per_cu(int N, int precision, int grad, int bw) {
+  return grad == kGradMixed ? step_blocks_per_cu_mixed(N, precision, bw)
+                            : step_blocks_per_cu_central(N, precision, bw);
+}
+
+hipError_t launch_step(int N, int precision, int grad, int bw, const StepArgs &a, int nblocks,
+                       hipStream_t st) {
+  return grad == kGradMixed ? launch_step_mixed(N, precision, bw, a, nblocks, st)
+                            : launch_step_central(N, precision, bw, a, nblocks, st);
+}
+#endif
 
 }  // namespace nplbm

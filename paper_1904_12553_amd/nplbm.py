@@ -129,10 +129,12 @@ def make_params(N, nx, ny, sigma, rho, mu, mobility=0.1, tau_phi=0.8, W=4.0, wal
     return p, keep
 
 
-def validate(N, sigma, rho, mu=None, mobility=0.1, tau_phi=0.8, W=4.0, nx=8, ny=8):
+def validate(N, sigma, rho, mu=None, mobility=0.1, tau_phi=0.8, W=4.0, nx=8, ny=8,
+             grad_scheme=0):
     """Host-only check of a parameter set; returns (lambda, beta2, K)."""
     mu = np.ones(N) if mu is None else mu
-    p, keep = make_params(N, nx, ny, sigma, rho, mu, mobility, tau_phi, W)
+    p, keep = make_params(N, nx, ny, sigma, rho, mu, mobility, tau_phi, W,
+                          grad_scheme=grad_scheme)
     lam = np.empty((N - 1) * (N - 1))
     b2, K = ctypes.c_double(), ctypes.c_double()
     _check(lib().nplbm_validate(ctypes.byref(p), _dp(lam), ctypes.byref(b2), ctypes.byref(K)))

@@ -72,6 +72,11 @@ def test_validate_rejects_bad_parameters():
     with pytest.raises(nb.NplbmError) as e:
         nb.validate(9, W.uniform_sigma(9, 1e-3), np.ones(9))
     assert e.value.code == -1
+    # gradient schemes: 0 (eq:N31a) and 1 (eq:N40) only
+    nb.validate(3, W.uniform_sigma(3, 1e-3), np.ones(3), grad_scheme=1)
+    with pytest.raises(nb.NplbmError) as e:
+        nb.validate(3, W.uniform_sigma(3, 1e-3), np.ones(3), grad_scheme=2)
+    assert e.value.code == -1
 
 
 def test_accepts_agrees_with_oracle():

@@ -175,6 +175,59 @@ def test_wall_ghosts_are_mirrors():
     assert g[1, 0, x] == pytest.approx((4 * (n - sth) + ne + nw - se - sw) / 12, abs=1e-13)
 
 
+def test_mixed_gradient_exact_on_quadratics():
+    """eq:N40 (two-hop term negative): per direction c the four-point
+    difference is exact to second order along c, and the D2Q9 weights turn
+    sum_k w_k c_k (c_k . grad f) / c_s^2 into grad f, so the stencil is exact
+    on quadratics; the Laplacian stays eq:N31b."""
+    s = sim(2, nx=40, ny=40, wall_y=False, grad_scheme=1)
+    y, x = np.mgrid[0:40, 0:40].astype(float)
+    a, b, c, d, e = 0.3, -0.7, 1.1, 0.2, -0.4
+    f = a * x * x + b * x * y + c * y * y + d * x + e * y
+    lap, g = s.stencils(f)
+    inner = (slice(3, -3), slice(3, -3))
+    assert np.allclose(lap[inner], 2 * a + 2 * c, atol=1e-10)
+    assert np.allclose(g[0][inner], (2 * a * x + b * y + d)[inner], atol=1e-10)
+    assert np.allclose(g[1][inner], (b * x + 2 * c * y + e)[inner], atol=1e-10)
+
+
+@pytest.mark.parametrize("m,n", [(1, 0), (2, 3), (5, 1), (7, 6)])
+def test_mixed_gradient_fourier_symbol(m, n):
+    """Symbol of eq:N40 on D2Q9 (derived by summing the eight directions of
+    exp(i k.x)): d/dx -> i [sin kx (1 + cos ky / 2) - sin 2kx (1 + cos 2ky / 2) / 6],
+    purely imaginary (the biased per-direction parts cancel in pairs)."""
+    nx = ny = 32
+    s = sim(2, nx=nx, ny=ny, grad_scheme=1)
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    kx, ky = 2 * np.pi * m / nx, 2 * np.pi * n / ny
+    f = np.cos(kx * x + ky * y)
+    _, g = s.stencils(f)
+    sx = np.sin(kx) * (1 + np.cos(ky) / 2) - np.sin(2 * kx) * (1 + np.cos(2 * ky) / 2) / 6
+    sy = np.sin(ky) * (1 + np.cos(kx) / 2) - np.sin(2 * ky) * (1 + np.cos(2 * kx) / 2) / 6
+    assert np.allclose(g[0], -sx * np.sin(kx * x + ky * y), atol=1e-13)
+    assert np.allclose(g[1], -sy * np.sin(kx * x + ky * y), atol=1e-13)
+
+
+def test_mixed_gradient_wall_ghosts_two_deep():
+    """Next to a wall the two-hop stencil reads mirror ghosts two rows deep:
+    zeta(x, -1) = zeta(x, 0), zeta(x, -2) = zeta(x, 1)."""
+    s = sim(2, nx=7, ny=6, wall_y=True, grad_scheme=1)
+    rng = np.random.default_rng(4)
+    f = rng.normal(size=(6, 7))
+    _, g = s.stencils(f)
+    fp = np.vstack([f[1::-1], f, f[:-3:-1]])   # two mirrored ghost rows each side
+
+    def z(x, y):
+        return fp[y + 2, x % 7]
+
+    for y in (0, 1, 5):
+        x = 3
+        gy = (24 * (z(x, y + 1) - z(x, y - 1)) - 4 * (z(x, y + 2) - z(x, y - 2)) +
+              6 * ((z(x + 1, y + 1) + z(x - 1, y + 1)) - (z(x + 1, y - 1) + z(x - 1, y - 1))) -
+              ((z(x + 2, y + 2) + z(x - 2, y + 2)) - (z(x + 2, y - 2) + z(x - 2, y - 2)))) / 48
+        assert g[1, y, x] == pytest.approx(gy, abs=1e-13)
+
+
 # ------------------------------------------------------ moment identities
 def test_geq_and_force_moments_eq_a1():
     """Moment conditions eq:a1a / eq:a1b (appendix)."""
@@ -270,9 +323,11 @@ def test_rho0_does_not_change_results():
 @pytest.mark.parametrize("N", [2, 3, 4, 5])
 @pytest.mark.parametrize("wall", [False, True])
 @pytest.mark.parametrize("shape", [(8, 8), (12, 10)])
-def test_c_oracle_matches_literal_transcription(N, wall, shape):
+@pytest.mark.parametrize("grad_scheme", [0, 1])
+def test_c_oracle_matches_literal_transcription(N, wall, shape, grad_scheme):
     nx, ny = shape
     w = W.random_smooth(N, nx, ny, seed=60 + N + nx, wall_y=wall, accept=oracle_accepts)
+    w.grad_scheme = grad_scheme
     a = OracleSim(**w.params())
     b = LiteralSim(**w.params())
     a.init(w.c, w.u)

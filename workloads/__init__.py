@@ -63,11 +63,12 @@ class Workload:
     steps: int = 1000
     precision: int = 64
     note: str = ""
+    grad_scheme: int = 0        # 0: eq:N31a central, 1: eq:N40 mixed
 
     def params(self) -> dict:
         return dict(N=self.N, nx=self.nx, ny=self.ny, sigma=self.sigma, rho=self.rho,
                     mu=self.mu, mobility=self.mobility, tau_phi=self.tau_phi, W=self.W,
-                    wall_y=self.wall_y, gx=self.gx, gy=self.gy)
+                    wall_y=self.wall_y, gx=self.gx, gy=self.gy, grad_scheme=self.grad_scheme)
 
 
 def uniform_sigma(N: int, value: float) -> np.ndarray:
@@ -170,6 +171,31 @@ def droplet_collision(side: int = 512, W: float = 4.0, seed: int = BASE_SEED + 3
     return Workload("droplet_collision_N4", 4, side, side, sigma, rho, 0.1 * rho, c, u,
                     mobility=0.1, tau_phi=0.8, W=W, steps=steps, precision=precision,
                     note=f"sigma redraws={redraws}")
+
+
+def five_phase_buoyancy(nx: int = 200, ny: int = 320, R: float = 30.0, W: float = 4.0,
+                        g: float = 1e-5, grad_scheme: int = 1, precision: int = 64,
+                        steps: int = 20000) -> Workload:
+    """N=5 droplets and interface under gravity (Sec. 4.4, eq:N39): phase 4
+    above phase 5 (interface at y0 = ny / 2), droplets of phases 1 and 2 at
+    (60, 280) and (140, 280) inside phase 4, a bubble of phase 3 at
+    (100, 40) inside phase 5 (positions for the 200 x 320 domain, scaled
+    with it); rho = 6 : 4 : 1 : 2 : 3, all sigma = 0.01, tau = 0.8 (mu =
+    0.1 rho), m = 0.1, W = 4 (eta = sqrt 2), gravity g downward (-y); walls
+    in y, periodic in x; the paper runs it with the mixed gradient scheme
+    of eq:N40."""
+    sx, sy = nx / 200.0, ny / 320.0
+    c1 = disc(nx, ny, 60 * sx, 280 * sy, R, W)
+    c2 = disc(nx, ny, 140 * sx, 280 * sy, R, W)
+    c3 = disc(nx, ny, 100 * sx, 40 * sy, R, W)
+    _, y = grid(nx, ny)
+    c5 = _profile(ny / 2.0 - y, W) * (1.0 - c3)
+    c4 = 1.0 - c1 - c2 - c3 - c5
+    rho = np.array([6.0, 4.0, 1.0, 2.0, 3.0])
+    return Workload("five_phase_buoyancy_N5", 5, nx, ny, uniform_sigma(5, 0.01), rho, 0.1 * rho,
+                    np.stack([c1, c2, c3, c4, c5]), None, mobility=0.1, tau_phi=0.8, W=W,
+                    wall_y=True, gy=-g, steps=steps, precision=precision,
+                    grad_scheme=grad_scheme)
 
 
 def bands_and_droplets(side: int = 2048, ndrop: int = 64, W: float = 4.0,
