@@ -114,3 +114,41 @@ def lens_shape(A, theta1, theta2):
     half = np.sqrt(A / s)
     h = half * (1.0 - np.cos(th)) / np.sin(th)
     return 2.0 * half, h[0], h[1]
+
+
+def puddle_thickness(c):
+    """Largest thickness of the phase-1 puddle over the columns: distance
+    between its lower and upper c_1 = 1/2 crossings."""
+    c1 = c[0]
+    ny, nx = c1.shape
+    best = 0.0
+    for x in range(nx):
+        v = c1[:, x]
+        if v.max() < 0.5:
+            continue
+        idx = np.where(v >= 0.5)[0]
+        lo, hi = idx[0], idx[-1]
+        if lo < 1 or hi + 1 >= ny:
+            continue
+        ylo = lo - (v[lo] - 0.5) / (v[lo] - v[lo - 1])
+        yhi = hi + (v[hi] - 0.5) / (v[hi] - v[hi + 1])
+        best = max(best, yhi - ylo)
+    return best
+
+
+def de_gennes_thickness(s12, s13, s23, rho1, rho2, rho3, g):
+    """Asymptotic thickness H of a large puddle of phase 1 floating between a
+    lighter phase 2 above and a heavier phase 3 below.  Isostasy fixes the
+    parts above and below the far-field level, a (rho_1 - rho_2) = b (rho_3 -
+    rho_1), and the excess hydrostatic pressure integrated over the puddle's
+    cross-section, g H^2 (rho_1 - rho_2)(rho_3 - rho_1) / (2 (rho_3 -
+    rho_2)), balances sigma_12 + sigma_13 - sigma_23.  With rho_2 = 0 this is
+    eq:N37."""
+    eff = (rho1 - rho2) * (rho3 - rho1) / (rho3 - rho2)
+    return np.sqrt(2.0 * (s12 + s13 - s23) / (eff * g))
+
+
+def centroid_velocity(c, u, k):
+    """Velocity of the centroid of phase k: sum c_k u / sum c_k."""
+    m = c[k].sum()
+    return (c[k] * u[0]).sum() / m, (c[k] * u[1]).sum() / m

@@ -8,7 +8,8 @@ import os
 import numpy as np
 import pytest
 
-from physics_util import lens_geometry, lens_shape, neumann_angles
+from physics_util import (de_gennes_thickness, lens_geometry, lens_shape, neumann_angles,
+                          puddle_thickness)
 
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "lens_table2.json")))
 
@@ -57,3 +58,24 @@ def test_half_disc_lens_is_measured_exactly():
     assert g["A"] == pytest.approx(np.pi * r * r, rel=0.01)
     d, h1, h2 = lens_shape(np.pi * r * r, 90.0, 90.0)
     assert (d, h1, h2) == pytest.approx((2 * r, r, r))
+
+
+def test_de_gennes_thickness_reduces_to_eq_N37():
+    # eq:N37 is the light-upper-phase limit rho_2 -> 0
+    s, g = 0.01, 1e-4
+    rho1, rho3 = 3.0, 6.0
+    eq37 = np.sqrt(2 * (s + s - s) / ((rho1 / rho3) * (rho3 - rho1) * g))
+    assert de_gennes_thickness(s, s, s, rho1, 0.0, rho3, g) == pytest.approx(eq37, rel=1e-14)
+    # a heavier upper phase makes the puddle thicker; H scales as g^(-1/2)
+    assert de_gennes_thickness(s, s, s, rho1, 1.0, rho3, g) > eq37
+    assert (de_gennes_thickness(s, s, s, 3, 1, 6, g) / de_gennes_thickness(s, s, s, 3, 1, 6, 4 * g)
+            == pytest.approx(2.0))
+
+
+def test_puddle_thickness_measure():
+    # a flat slab of phase 1 with linear ramps: thickness between crossings
+    ny, nx = 60, 50
+    y = np.arange(ny, dtype=float)[:, None] * np.ones((1, nx))
+    c1 = np.clip(np.minimum(y - 20.3, 35.8 - y) / 3.0 + 0.5, 0.0, 1.0)
+    c = np.stack([c1, 1 - c1, np.zeros_like(c1)])
+    assert puddle_thickness(c) == pytest.approx(15.5, abs=1e-9)

@@ -173,6 +173,54 @@ def droplet_collision(side: int = 512, W: float = 4.0, seed: int = BASE_SEED + 3
                     note=f"sigma redraws={redraws}")
 
 
+def floating_puddle(nx: int = 400, ny: int = 200, R: float = 30.0, W: float = 4.0,
+                    g: float = 1e-4, sigma=(0.01, 0.01, 0.01), rho=(3.0, 1.0, 6.0),
+                    precision: int = 64, steps: int = 200000) -> Workload:
+    """A phase-1 droplet at the flat interface between a light phase 2 (top)
+    and a heavy phase 3 (bottom), eq:N35 layout, under gravity g downward
+    (-y), walls in y (Sec. 4.2, second part): rho = 3 : 1 : 6, sigma_12 :
+    sigma_13 : sigma_23 = 1 : 1 : 1 (0.01), tau = 0.8 (mu = 0.1 rho), m =
+    0.1, W = 4.  For large g it flattens into a puddle whose thickness tends
+    to eq:N37."""
+    xc, yc = nx / 2.0, ny / 2.0
+    c1 = disc(nx, ny, xc, yc, R, W)
+    _, y = grid(nx, ny)
+    c2 = np.maximum(_profile(y - yc, W) - c1, 0.0)
+    c3 = 1.0 - c1 - c2
+    s12, s13, s23 = sigma
+    sig = np.array([[0.0, s12, s13], [s12, 0.0, s23], [s13, s23, 0.0]])
+    rho = np.asarray(rho, dtype=float)
+    return Workload("floating_puddle_N3", 3, nx, ny, sig, rho, 0.1 * rho,
+                    np.stack([c1, c2, c3]), None, mobility=0.1, tau_phi=0.8, W=W,
+                    wall_y=True, gy=-g, steps=steps, precision=precision)
+
+
+def four_phase_buoyancy(nx: int = 200, ny: int = 320, D: float = 60.0, W: float = 4.0,
+                        sigma13: float = 0.01, g: float = 1e-5, precision: int = 64,
+                        steps: int = 30000, grad_scheme: int = 0) -> Workload:
+    """N=4 droplet and bubble under gravity (Sec. 4.3, eq:N38): phase 3 above
+    phase 4 (interface at y0 = ny / 2), a phase-1 droplet of diameter D at
+    (160, 280) inside phase 3 and a phase-2 bubble at (160, 40) inside phase
+    4 (the printed centres; x is periodic, so only their common column
+    matters), scaled with the domain; rho = 6 : 1 : 3 : 2, sigma_13 varied,
+    every other sigma 0.01, tau = 0.8 (mu = 0.1 rho), m = 0.1, W = 4, g
+    downward (-y); walls in y, periodic in x."""
+    sx, sy = nx / 200.0, ny / 320.0
+    R = D / 2.0
+    c1 = disc(nx, ny, (160 * sx) % nx, 280 * sy, R, W)
+    c2 = disc(nx, ny, (160 * sx) % nx, 40 * sy, R, W)
+    _, y = grid(nx, ny)
+    c3 = _profile(y - ny / 2.0, W) * (1.0 - c1)
+    c4 = 1.0 - c1 - c2 - c3
+    sig = uniform_sigma(4, 0.01)
+    sig[0, 2] = sig[2, 0] = sigma13
+    rho = np.array([6.0, 1.0, 3.0, 2.0])
+    return Workload("four_phase_buoyancy_N4", 4, nx, ny, sig, rho, 0.1 * rho,
+                    np.stack([c1, c2, c3, c4]), None, mobility=0.1, tau_phi=0.8, W=W,
+                    wall_y=True, gy=-g, steps=steps, precision=precision,
+                    grad_scheme=grad_scheme)
+
+
 def five_phase_buoyancy(nx: int = 200, ny: int = 320, R: float = 30.0, W: float = 4.0,
                         g: float = 1e-5, grad_scheme: int = 1, precision: int = 64,
                         steps: int = 20000) -> Workload:
