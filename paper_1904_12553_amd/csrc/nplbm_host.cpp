@@ -311,7 +311,11 @@ int64_t row_pad(size_t elem) {
   return (int64_t)(kRowPadBytes / elem);
 }
 
-// Workgroups the step kernel can keep resident on the device at once.
+// Workgroups the step kernel keeps resident on the device at once: as many
+// as the registers allow, up to 8 waves per compute unit.  A 16-wave
+// configuration (two 8-wave FP32 workgroups at N = 3) measured 4 points of
+// the HBM roofline slower than one: twice as many concurrent row streams and
+// half-height strips, for no gain in bytes in flight.
 int resident_step_blocks(int N, int precision, int grad) {
   static int cus = -1;
   if (cus < 0) {
@@ -322,8 +326,10 @@ int resident_step_blocks(int N, int precision, int grad) {
     else
       cus = 0;
   }
-  const int per = step_blocks_per_cu(N, precision, grad, step_geom(N, precision, grad).bw);
-  return cus > 0 && per > 0 ? cus * per : 0;
+  const int bw = step_geom(N, precision, grad).bw;
+  const int per = step_blocks_per_cu(N, precision, grad, bw);
+  const int cap = std::max(1, 8 / std::max(1, bw * kRows / 64));
+  return cus > 0 && per > 0 ? cus * std::min(per, cap) : 0;
 }
 
 // Strip count for a single-domain launch: one full round of resident

@@ -54,28 +54,42 @@ namespace nplbm {
 
 // Address spaces: the descriptors and constants are read-only for the whole
 // launch and uniform per workgroup, so they are read through constant
-// (scalar-load) pointers; the state arrays are global-memory pointers so the
-// loads are global (not flat) loads with a per-plane scalar base and one
-// shared 32-bit lane offset.
-#define NPL_GLOBAL __attribute__((address_space(1)))
+// (scalar-load) pointers.
 #define NPL_CONST __attribute__((address_space(4)))
 
-// Element access by 32-bit byte offset from a (scalar) plane base, so that
-// every access is one global load/store with an SGPR base and a VGPR offset
-// shared by all planes (the host guarantees planes are below 4 GiB).
+// State access through buffer instructions.  In the row-interleaved layout
+// one row of a state group (all its planes) is one contiguous block, so a
+// buffer resource is built per (group, row) in scalar registers, and an
+// element is addressed by a scalar plane offset plus a per-lane column
+// offset shared by all planes: one buffer_load / buffer_store per value
+// with no per-access vector address arithmetic.  The resource's size is the
+// row block, so an offset outside it reads 0 / drops the store instead of
+// touching other memory.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+constexpr int kRsrcWord3 = 0x00020000;  // gfx9 raw buffer: 32-bit data format
+
+__device__ __forceinline__ Rsrc row_rsrc(const void *base, uint32_t row_bytes, int y) {
+  return __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<char *>(static_cast<const char *>(base)) + (size_t)y * row_bytes, (short)0,
+      (int)row_bytes, kRsrcWord3);
+}
 template <typename Real>
-__device__ __forceinline__ Real ld(const NPL_GLOBAL Real *base, uint32_t boff) {
-  return *(const NPL_GLOBAL Real *)((const NPL_GLOBAL char *)base + boff);
+__device__ __forceinline__ Real bld(Rsrc r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(Real) == 8)
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  else
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
 // Stores of the new state are never read again within the step; FP64 runs
 // measured faster with them marked nontemporal (streaming), FP32 slower.
 template <typename Real>
-__device__ __forceinline__ void st(NPL_GLOBAL Real *base, uint32_t boff, Real v) {
-  NPL_GLOBAL Real *p = (NPL_GLOBAL Real *)((NPL_GLOBAL char *)base + boff);
+__device__ __forceinline__ void bst(Rsrc r, uint32_t voff, uint32_t soff, Real v) {
+  typedef unsigned u2 __attribute__((ext_vector_type(2)));
+  constexpr int kNontemporal = 2;  // cache-policy bit nt of gfx94x/gfx950
   if constexpr (sizeof(Real) == 8)
-    __builtin_nontemporal_store(v, p);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, kNontemporal);
   else
-    *p = v;
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
 }
 
 #ifndef NPL_WAVES_PER_EU
@@ -136,8 +150,6 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   constexpr int M = N - 1;
   using S = Scheme<kGS>;
   constexpr int kPR = S::kPR, kCR = S::kCR, kHalo = S::kHalo;
-  typedef const NPL_GLOBAL Real *GIn;
-  typedef NPL_GLOBAL Real *GOut;
   const NPL_CONST StripDesc *sp = (const NPL_CONST StripDesc *)a.strips + blockIdx.x;
   StripDesc sd;
   sd.dom = sp->dom;
@@ -150,18 +162,18 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   const NPL_CONST DomDesc *D = (const NPL_CONST DomDesc *)a.doms + sd.dom;
   if (a.substep >= D->steps_left) return;
   const int par = (a.substep + D->parity0) & 1;
-  const GIn hs = (GIn)D->h[par];
-  const GOut hd = (GOut)D->h[par ^ 1];
-  const GIn gs = (GIn)D->g[par];
-  const GOut gd = (GOut)D->g[par ^ 1];
-  const GIn pvs = (GIn)D->prev[par];
-  const GOut pvd = (GOut)D->prev[par ^ 1];
+  const void *hs = D->h[par], *hd = D->h[par ^ 1];
+  const void *gs = D->g[par], *gd = D->g[par ^ 1];
+  const void *pvs = D->prev[par], *pvd = D->prev[par ^ 1];
   const NPL_CONST Consts<Real> &K = *consts_of<Real>(D);
   const int nx = D->nx, ny = D->ny;
   const bool wall = D->wall != 0;
-  // element strides between planes and between rows of each state group
-  const size_t psh = (size_t)D->ps[0], psg = (size_t)D->ps[1], psp = (size_t)D->ps[2];
-  const size_t rsh = (size_t)D->rs[0], rsg = (size_t)D->rs[1], rsp = (size_t)D->rs[2];
+  // bytes between planes (the row pitch, the same in every group) and
+  // bytes of one row block of each state group
+  constexpr uint32_t SZ = sizeof(Real);
+  const uint32_t pb = (uint32_t)D->ps[0] * SZ;
+  const uint32_t rbh = (uint32_t)D->rs[0] * SZ, rbg = (uint32_t)D->rs[1] * SZ,
+                 rbp = (uint32_t)D->rs[2] * SZ;
 
   __shared__ Real sphi[kPR][M][kBW];
   __shared__ Real sC[kCR][M][kBW];
@@ -173,7 +185,6 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   const int xl = sd.x0 - kHalo + lane;
   int xc = xl % nx;
   if (xc < 0) xc += nx;
-  constexpr uint32_t SZ = sizeof(Real);
   const uint32_t xcu = (uint32_t)xc * SZ;                              // byte offsets
   const uint32_t xw = (xc == 0 ? (uint32_t)(nx - 1) : (uint32_t)xc - 1) * SZ;  // x - 1
   const uint32_t xe = (xc == nx - 1 ? 0u : (uint32_t)xc + 1) * SZ;             // x + 1
@@ -213,13 +224,14 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
     s.yN = yN >= ny ? yN - ny : yN;
     return s;
   };
-  // source row (returned), direction kk and column byte offset co of k
+  // source row block (returned: 0 own row, 1 row below, 2 row above),
+  // direction kk and column byte offset co of k
   auto src_of = [&](const Src &s, int k, int &kk, uint32_t &co) -> int {
     const int cx = cxk(k), cy = cyk(k);
     const bool b = (cy == 1 && s.bS) || (cy == -1 && s.bN);
     kk = b ? oppk(k) : k;
     co = b ? xcu : (cx == 1 ? xw : (cx == -1 ? xe : xcu));
-    return b ? s.y0 : (cy == 1 ? s.yS : (cy == -1 ? s.yN : s.y0));
+    return b ? 0 : (cy == 1 ? 1 : (cy == -1 ? 2 : 0));
   };
 
   // lo part of phi_i: the stored deviation of h_0 plus the moving populations
@@ -234,31 +246,38 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   auto pull_ch = [&](int m, Pulled<M, Real> &P) {
     const int yp = phys_row(row_of(m));
     const Src s = make_src(yp);
+    const Rsrc r0 = row_rsrc(hs, rbh, s.y0), rS = row_rsrc(hs, rbh, s.yS),
+               rN = row_rsrc(hs, rbh, s.yN);
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
       int kk;
       uint32_t co;
-      const int ys = src_of(s, k, kk, co);
+      const int w = src_of(s, k, kk, co);
+      const Rsrc r = w == 1 ? rS : (w == 2 ? rN : r0);
 #pragma unroll
-      for (int i = 0; i < M; ++i)
-        P.h[i][k] = ld(hs + (size_t)(i * 9 + kk) * psh + (size_t)ys * rsh, co);
+      for (int i = 0; i < M; ++i) P.h[i][k] = bld<Real>(r, co, (uint32_t)(i * 9 + kk) * pb);
     }
+    const Rsrc rp = row_rsrc(pvs, rbp, yp);
 #pragma unroll
-    for (int i = 0; i < M; ++i) P.hi[i] = ld(pvs + (size_t)i * psp + (size_t)yp * rsp, xcu);
+    for (int i = 0; i < M; ++i) P.hi[i] = bld<Real>(rp, xcu, (uint32_t)i * pb);
   };
   // ---- pull the NS populations and stored u of march index m ----
   auto pull_ns = [&](int m, PulledNS<Real> &Q) {
     const int yp = phys_row(row_of(m));
     const Src s = make_src(yp);
+    const Rsrc r0 = row_rsrc(gs, rbg, s.y0), rS = row_rsrc(gs, rbg, s.yS),
+               rN = row_rsrc(gs, rbg, s.yN);
 #pragma unroll
     for (int k = 1; k < 9; ++k) {
       int kk;
       uint32_t co;
-      const int ys = src_of(s, k, kk, co);
-      Q.g[k] = ld(gs + (size_t)(kk - 1) * psg + (size_t)ys * rsg, co);
+      const int w = src_of(s, k, kk, co);
+      const Rsrc r = w == 1 ? rS : (w == 2 ? rN : r0);
+      Q.g[k] = bld<Real>(r, co, (uint32_t)(kk - 1) * pb);
     }
-    Q.pu[0] = ld(pvs + (size_t)M * psp + (size_t)yp * rsp, xcu);
-    Q.pu[1] = ld(pvs + (size_t)(M + 1) * psp + (size_t)yp * rsp, xcu);
+    const Rsrc rp = row_rsrc(pvs, rbp, yp);
+    Q.pu[0] = bld<Real>(rp, xcu, (uint32_t)M * pb);
+    Q.pu[1] = bld<Real>(rp, xcu, (uint32_t)(M + 1) * pb);
   };
 
   // ---- stage A: phi of march index mA -> LDS ----
@@ -424,9 +443,8 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
     // isotropic part of eq:N20_1: u.grad(rho) - tr(T) / (2 c_s^2)
     const Real gbase =
         udr - Real(1.5) * (Real(2) * uF + Real(2) / Real(3) * udr + theta * Ju);
-    const GOut hrow = hd + (size_t)yp * rsh;
-    const GOut grow = gd + (size_t)yp * rsg;
-    const GOut prow = pvd + (size_t)yp * rsp;
+    const Rsrc wh = row_rsrc(hd, rbh, yp), wg = row_rsrc(gd, rbg, yp),
+               wp = row_rsrc(pvd, rbp, yp);
 #pragma unroll
     for (int k = 1; k < 9; ++k) {
       const Real cx = Real(cxk(k)), cy = Real(cyk(k));
@@ -440,7 +458,7 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
       const Real G =
           w * (gbase + Real(3) * cF +
                Real(4.5) * cu * (Real(2) * cF + Real(2) / Real(3) * cr + theta * cJ));
-      st(grow + (size_t)(k - 1) * psg, xcu, g[k] - itau * (g[k] - geq) + srcg * G);
+      bst<Real>(wg, xcu, (uint32_t)(k - 1) * pb, g[k] - itau * (g[k] - geq) + srcg * G);
     }
     // CH collisions
     const Real pux = Q.pu[0], puy = Q.pu[1];
@@ -460,7 +478,7 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
         const Real R = sr * w * Real(3) * (cx * dx + cy * dy);         // eq:N26
         const Real hn = P.h[i][k] - it * (P.h[i][k] - heq) + R;
         hsum += hn;
-        st(hrow + (size_t)(i * 9 + k) * psh, xcu, hn);
+        bst<Real>(wh, xcu, (uint32_t)(i * 9 + k) * pb, hn);
       }
       // phi_i = hi + lo exactly; phi[i] = fl(hi + lo) is stored as the new
       // previous phi and the k = 0 slot keeps (hi + lo - phi[i]) - sum h_k
@@ -468,11 +486,11 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
       const Real lo = lo_sum(P.h[i]);
       const Real bb = phi[i] - pp;
       const Real err = (pp - (phi[i] - bb)) + (lo - bb);
-      st(hrow + (size_t)(i * 9) * psh, xcu, err - hsum);
-      st(prow + (size_t)i * psp, xcu, phi[i]);
+      bst<Real>(wh, xcu, (uint32_t)(i * 9) * pb, err - hsum);
+      bst<Real>(wp, xcu, (uint32_t)i * pb, phi[i]);
     }
-    st(prow + (size_t)M * psp, xcu, ux);
-    st(prow + (size_t)(M + 1) * psp, xcu, uy);
+    bst<Real>(wp, xcu, (uint32_t)M * pb, ux);
+    bst<Real>(wp, xcu, (uint32_t)(M + 1) * pb, uy);
   };
 
   // March over iterations j (march index mA = 2j - kRamp + row).  Each does
