@@ -34,7 +34,7 @@ def _lib():
         lib = ctypes.CDLL(path)
         d, i, l, vp = ctypes.c_double, ctypes.c_int, ctypes.c_long, ctypes.c_void_p
         P = ctypes.POINTER(ctypes.c_double)
-        lib.orc_create.argtypes = [i, i, i, i, i, P, P, P, P, P, d, d, d, d,
+        lib.orc_create.argtypes = [i, i, i, i, i, i, P, P, P, P, P, d, d, d, d,
                                    ctypes.POINTER(vp)]
         lib.orc_create.restype = i
         lib.orc_free.argtypes = [vp]
@@ -84,10 +84,13 @@ class OracleSim:
     dynamic viscosities ``mu`` (N each), CH mobility ``mobility`` and
     relaxation time ``tau_phi`` (scalars or N-1 values), interface width
     ``W`` (= 2 sqrt(2) eta), body-force acceleration ``(gx, gy)``.
+    ``force_form`` 0 is the total-force distribution of eq:N20_1, 1 the one
+    of Remark 1 (Sec. 3.1) with F = -div(J~ u) + F_s + G; 2 is a planted
+    mistake of form 1 (indices of the divergence swapped) that only tests use.
     """
 
     def __init__(self, N, nx, ny, sigma, rho, mu, mobility=0.1, tau_phi=0.8,
-                 W=4.0, wall_y=False, gx=0.0, gy=0.0, rho0=1.0, grad_scheme=0):
+                 W=4.0, wall_y=False, gx=0.0, gy=0.0, rho0=1.0, grad_scheme=0, force_form=0):
         lib = _lib()
         self.N, self.nx, self.ny = int(N), int(nx), int(ny)
         sig = np.ascontiguousarray(np.asarray(sigma, dtype=np.float64).reshape(N, N))
@@ -97,7 +100,7 @@ class OracleSim:
         tp = _arr(tau_phi, N - 1)
         h = ctypes.c_void_p()
         rc = lib.orc_create(self.N, self.nx, self.ny, int(bool(wall_y)), int(grad_scheme),
-                            _p(sig), _p(r), _p(m), _p(mob), _p(tp), float(W),
+                            int(force_form), _p(sig), _p(r), _p(m), _p(mob), _p(tp), float(W),
                             float(gx), float(gy), float(rho0), ctypes.byref(h))
         if rc != 0:
             raise OracleError(rc)

@@ -9,8 +9,10 @@ C oracle.
 
 Equations: eq:N1, eq:N12, eq:N14-N18, eq:N36 (setup and closure);
 eq:N31a/b (stencils), eq:N40 (mixed gradient, two-hop term read as
-negative); eq:24, eq:25, eq:N20_1, eq:N21_1, eq:N22_1, eq:N23
-(NS part); eq:N24-N28, eq:N30 (CH part).
+negative); eq:24, eq:25, eq:N20_1 or the force distribution of Remark 1
+(Sec. 3.1, with div(J~ u) taken over J~ of the step and the stored u of the
+previous step), eq:N21_1, eq:N22_1, eq:N23 (NS part); eq:N24-N28, eq:N30
+(CH part).
 """
 from __future__ import annotations
 
@@ -24,9 +26,10 @@ CS2 = 1.0 / 3.0
 
 class LiteralSim:
     def __init__(self, N, nx, ny, sigma, rho, mu, mobility=0.1, tau_phi=0.8, W=4.0,
-                 wall_y=False, gx=0.0, gy=0.0, rho0=1.0, grad_scheme=0):
+                 wall_y=False, gx=0.0, gy=0.0, rho0=1.0, grad_scheme=0, force_form=0):
         self.N, self.nx, self.ny = N, nx, ny
         self.grad_scheme = int(grad_scheme)
+        self.force_form = int(force_form)
         self.sig = np.asarray(sigma, float).reshape(N, N)
         self.rt = np.asarray(rho, float) * np.ones(N)
         self.mt = np.asarray(mu, float) * np.ones(N)
@@ -170,6 +173,10 @@ class LiteralSim:
         F = np.einsum("iyx,idyx->dyx", Cp, gphi) + rho[None] * self.G[:, None, None]
         coef = (1 - self.N * self.gam[:-1] / self.Gam) * self.a * self.m
         J = -np.einsum("i,idyx->dyx", coef, gC)
+        if self.force_form == 1:
+            # Remark 1: F -= div(J~ u_prev), (div)_a = sum_b d_b (J~_b u_a)
+            for a in range(2):
+                F[a] -= sum(self.grad(J[b] * self.pu[a])[b] for b in range(2))
         mom = np.einsum("kd,kyx->dyx", C.astype(float), self.g)
         u = (mom + 0.5 * F) / rho                                # eq:N22_1
         uu = u[0] ** 2 + u[1] ** 2
@@ -193,7 +200,8 @@ class LiteralSim:
                 for al in range(2):
                     for be in range(2):
                         T[al, be] = (u[al] * F[be] + F[al] * u[be] + CS2 * (u[al] * grho[be] +
-                                     grho[al] * u[be]) + J[al] * u[be] / (tg - 0.5))
+                                     grho[al] * u[be]) +
+                                     (J[al] * u[be] / (tg - 0.5) if self.force_form == 0 else 0.0))
                 con = sum((ck[al] * ck[be] - CS2 * (al == be)) * T[al, be]
                           for al in range(2) for be in range(2))
                 Gk = WGT[k] * ((u * grho).sum(axis=0) + (ck[0] * F[0] + ck[1] * F[1]) / CS2 +

@@ -18,7 +18,9 @@
  *   - stencils: eq:N31a / eq:N31b (isotropic central first derivative and
  *               Laplacian, written as the sum over the D2Q9 velocities)
  *   - NS LBE  : eq:24 with g^eq of eq:25 and the total-force distribution
- *               G_k of eq:N20_1; u from eq:N22_1, p from eq:N23,
+ *               G_k of eq:N20_1 (force_form 0) or of Remark 1 in Sec. 3.1
+ *               (force_form 1: F carries -div(J~ u) and the tensor part has
+ *               no J~ u term); u from eq:N22_1, p from eq:N23,
  *               tau_g from eq:N21_1 with mu = sum_k mu~_k c_k (Sec. 2)
  *   - CH LBEs : eq:N24 with h^eq of eq:N25, source R_k of eq:N26 and the
  *               backward-Euler time derivative of eq:N27; phi_i by eq:N28
@@ -37,7 +39,12 @@
  *   - tau_g varies per node as 1/2 + mu/(rho c_s^2), mu = sum mu~_k c_k;
  *   - the body force is G = rho (gx, gy);
  *   - grad(rho) is the eq:N31a stencil applied to the rho field;
- *   - no clipping of c or phi.
+ *   - no clipping of c or phi;
+ *   - Remark 1's div(J~ u) is component a = sum_b d_b (J~_b u_a), with J~
+ *     of the current step and u of the previous step (the stored u of the
+ *     source term eq:N27): u of the current step would need the force at the
+ *     neighbours, which itself contains the term.  The derivative is the
+ *     same first-derivative stencil as every other gradient.
  *
  * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared (see build_oracle.py).
  * The OpenMP loops only split independent per-node work across threads;
@@ -62,7 +69,7 @@ static const double CS2 = 1.0 / 3.0;
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOTSPD = -2, ORC_ENOMEM = -3 };
 
 typedef struct orc_sim {
-  int N, nx, ny, wall_y, grad_scheme;
+  int N, nx, ny, wall_y, grad_scheme, force_form;
   double rho_t[NMAX], mu_t[NMAX];
   double sigma[NMAX][NMAX];
   double mob[NMAX], tau[NMAX]; /* CH mobility m_i and relaxation tau_i */
@@ -78,6 +85,7 @@ typedef struct orc_sim {
   double *pu;    /* previous u        [2][ny*nx]     */
   /* scratch (macroscopic fields of the current step) */
   double *phi, *c, *rho, *Cp, *lap, *gphi, *gC, *grho, *F, *J, *u, *p, *taug;
+  double *q; /* Remark 1: the four products J~_b u_a of the previous u */
   double *hs, *gs; /* post-collision */
 } orc_sim;
 
@@ -211,8 +219,11 @@ static double g_eq(const orc_sim *s, int k, double rho, double p, double ux,
 }
 
 /* eq:N20_1, contracted as written: (c c - cs^2 I) : T / (2 cs^4) with
-   T = uF + Fu + cs^2 (u grad rho + grad rho u) + J u / (tau_g - 1/2). */
-static double G_force(int k, double ux, double uy, double Fx, double Fy,
+   T = uF + Fu + cs^2 (u grad rho + grad rho u) + J u / (tau_g - 1/2).
+   form 1: the distribution of Remark 1 (Sec. 3.1), the same without the
+   J u / (tau_g - 1/2) term (F then carries -div(J u)); form 2 is form 1
+   with a planted mistake (see macroscopic). */
+static double G_force(int form, int k, double ux, double uy, double Fx, double Fy,
                       double rx, double ry, double Jx, double Jy,
                       double taug) {
   double u[2] = {ux, uy}, F[2] = {Fx, Fy}, r[2] = {rx, ry}, J[2] = {Jx, Jy};
@@ -221,7 +232,8 @@ static double G_force(int k, double ux, double uy, double Fx, double Fy,
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b)
       T[a][b] = u[a] * F[b] + F[a] * u[b] + CS2 * u[a] * r[b] +
-                CS2 * r[a] * u[b] + J[a] * u[b] / (1.0 * (taug - 0.5));
+                CS2 * r[a] * u[b] +
+                (form != 0 ? 0.0 : J[a] * u[b] / (1.0 * (taug - 0.5)));
   double contr = 0.0;
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b)
@@ -337,21 +349,23 @@ void orc_free(orc_sim *s) {
   free(s->h); free(s->g); free(s->pphi); free(s->pu);
   free(s->phi); free(s->c); free(s->rho); free(s->Cp); free(s->lap);
   free(s->gphi); free(s->gC); free(s->grho); free(s->F); free(s->J);
-  free(s->u); free(s->p); free(s->taug); free(s->hs); free(s->gs);
+  free(s->u); free(s->p); free(s->taug); free(s->hs); free(s->gs); free(s->q);
   free(s);
 }
 
 int orc_create(int N, int nx, int ny, int wall_y, int grad_scheme,
-               const double *sigma, const double *rho, const double *mu,
+               int force_form, const double *sigma, const double *rho, const double *mu,
                const double *mob, const double *tau_phi, double W, double gx,
                double gy, double rho0, orc_sim **out) {
   *out = NULL;
   if (N < 2 || N > NMAX || nx < 4 || ny < 4 || !(W > 0.0)) return ORC_EINVAL;
   if (grad_scheme != 0 && grad_scheme != 1) return ORC_EINVAL;
+  if (force_form < 0 || force_form > 2) return ORC_EINVAL;
   orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));
   if (!s) return ORC_ENOMEM;
   s->N = N; s->nx = nx; s->ny = ny; s->wall_y = wall_y ? 1 : 0;
   s->grad_scheme = grad_scheme;
+  s->force_form = force_form;
   for (int k = 0; k < N; ++k) {
     if (!(rho[k] > 0.0) || !(mu[k] > 0.0)) { orc_free(s); return ORC_EINVAL; }
     s->rho_t[k] = rho[k];
@@ -411,9 +425,10 @@ int orc_create(int N, int nx, int ny, int wall_y, int grad_scheme,
   s->taug = calloc(n, sizeof(double));
   s->hs = calloc((size_t)n1 * Q * n, sizeof(double));
   s->gs = calloc((size_t)Q * n, sizeof(double));
+  s->q = calloc(4 * n, sizeof(double));
   if (!s->h || !s->g || !s->pphi || !s->pu || !s->phi || !s->c || !s->rho ||
       !s->Cp || !s->lap || !s->gphi || !s->gC || !s->grho || !s->F || !s->J ||
-      !s->u || !s->p || !s->taug || !s->hs || !s->gs) {
+      !s->u || !s->p || !s->taug || !s->hs || !s->gs || !s->q) {
     orc_free(s);
     return ORC_ENOMEM;
   }
@@ -482,7 +497,7 @@ static void macroscopic(orc_sim *s) {
       }
       grad(s, s->rho, x, y, &s->grho[id], &s->grho[n + id]);
     }
-  /* forces, flux, velocity, pressure */
+  /* forces and flux */
   #pragma omp parallel for schedule(static) if (s->nx * s->ny >= 8192)
   for (size_t x = 0; x < n; ++x) {
     double Fx = 0.0, Fy = 0.0, Jx = 0.0, Jy = 0.0;
@@ -500,6 +515,37 @@ static void macroscopic(orc_sim *s) {
     Fy += r * s->gy;
     s->F[x] = Fx; s->F[n + x] = Fy;
     s->J[x] = Jx; s->J[n + x] = Jy;
+  }
+  /* Remark 1 (Sec. 3.1): F = -div(J~ u) + F_s + G, component a of the
+     divergence being sum_b d_b (J~_b u_a), with the previous step's u */
+  if (s->force_form != 0) {
+    /* force_form 2 is a PLANTED MISTAKE for the tests only: the divergence
+       taken over the other index, sum_b d_b (J~_a u_b), which a test must be
+       able to tell apart from the correct form */
+    const int swap = s->force_form == 2;
+    for (size_t x = 0; x < n; ++x) {
+      s->q[x] = s->J[x] * s->pu[x];                    /* J_x u_x */
+      s->q[n + x] = swap ? s->J[x] * s->pu[n + x] : s->J[n + x] * s->pu[x]; /* J_y u_x */
+      s->q[2 * n + x] = swap ? s->J[n + x] * s->pu[x] : s->J[x] * s->pu[n + x]; /* J_x u_y */
+      s->q[3 * n + x] = s->J[n + x] * s->pu[n + x];    /* J_y u_y */
+    }
+    #pragma omp parallel for schedule(static) if (s->nx * s->ny >= 8192)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        size_t id = (size_t)y * nx + x;
+        double axx, axy, ayx, ayy, bxx, bxy, byx, byy;
+        grad(s, s->q, x, y, &axx, &axy);          /* d/dx, d/dy of J_x u_x */
+        grad(s, s->q + n, x, y, &ayx, &ayy);      /* of J_y u_x */
+        grad(s, s->q + 2 * n, x, y, &bxx, &bxy);  /* of J_x u_y */
+        grad(s, s->q + 3 * n, x, y, &byx, &byy);  /* of J_y u_y */
+        s->F[id] -= axx + ayy;
+        s->F[n + id] -= bxx + byy;
+      }
+  }
+  /* velocity and pressure */
+  #pragma omp parallel for schedule(static) if (s->nx * s->ny >= 8192)
+  for (size_t x = 0; x < n; ++x) {
+    double Fx = s->F[x], Fy = s->F[n + x], r = s->rho[x];
     double mx = 0.0, my = 0.0;
     for (int k = 0; k < Q; ++k) {
       mx += CX[k] * s->g[(size_t)k * n + x];
@@ -603,7 +649,7 @@ int orc_step(orc_sim *s, long nsteps) {
       double tg = s->taug[x];
       for (int k = 0; k < Q; ++k) {
         double geq = g_eq(s, k, r, p, ux, uy);
-        double G = G_force(k, ux, uy, s->F[x], s->F[n + x], s->grho[x],
+        double G = G_force(s->force_form, k, ux, uy, s->F[x], s->F[n + x], s->grho[x],
                            s->grho[n + x], s->J[x], s->J[n + x], tg);
         double gk = s->g[(size_t)k * n + x];
         s->gs[(size_t)k * n + x] = gk - (gk - geq) / tg + (1.0 - 1.0 / (2.0 * tg)) * G;
@@ -725,7 +771,7 @@ int orc_node_dists(const orc_sim *s, double rho, double p, double ux, double uy,
                    double Jy, double taug, double *geq, double *G) {
   for (int k = 0; k < Q; ++k) {
     geq[k] = g_eq(s, k, rho, p, ux, uy);
-    G[k] = G_force(k, ux, uy, Fx, Fy, rx, ry, Jx, Jy, taug);
+    G[k] = G_force(s->force_form, k, ux, uy, Fx, Fy, rx, ry, Jx, Jy, taug);
   }
   return ORC_OK;
 }
