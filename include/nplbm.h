@@ -59,6 +59,15 @@ enum {
  *                   -zeta(x + 2 c_i) (printed with a + sign, which would make
  *                   it twice the gradient).  The Laplacian is eq:N31b in
  *                   both.  Other values: NPLBM_EINVAL.
+ *   force_form      total-force distribution of the NS equation: 0 = G_k of
+ *                   eq:N20_1 (the J~ u / (tau_g - 1/2) term in its second
+ *                   moment); 1 = the alternative of Remark 1 (Sec. 3.1): G_k
+ *                   without that term and F = -div(J~ u) + F_s + G, component
+ *                   a of the divergence being sum_b d_b (J~_b u_a) by the
+ *                   eq:N31a stencil, with J~ of the current step and u of
+ *                   the previous step (the stored u of eq:N27).  Built with
+ *                   grad_scheme 0 only; other values or combinations:
+ *                   NPLBM_EINVAL.
  *   sigma           N*N row-major pairwise tensions sigma_kl > 0, symmetric;
  *                   the diagonal is ignored
  *   rho, mu         N densities rho~_k > 0 and dynamic viscosities mu~_k > 0
@@ -78,6 +87,7 @@ typedef struct nplbm_params {
   int32_t wall_y;
   int32_t precision;
   int32_t grad_scheme;
+  int32_t force_form;
   const double *sigma;
   const double *rho;
   const double *mu;

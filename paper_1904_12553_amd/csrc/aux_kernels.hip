@@ -216,10 +216,39 @@ __global__ void k_macro_phi(const DomDesc *dd, int M, int parity, double *phi, d
     }
 }
 
-// u (eq:N22_1) and p (eq:N23) in FP64
+// Remark 1 (Sec. 3.1): the products J~_b u_a, J~ from the eq:N31a
+// gradients of C (eq:N18 line 4) and u the stored velocity of the previous
+// step; planes q[0..3] = J~_x u_x, J~_y u_x, J~_x u_y, J~_y u_y.
+template <typename Real>
+__global__ void k_macro_q(const DomDesc *dd, int M, int parity, const double *C, double *q) {
+  const int nx = dd->nx, ny = dd->ny;
+  const int64_t n = (int64_t)nx * ny;
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= n) return;
+  const int x = (int)(id % nx), y = (int)(id / nx);
+  const bool wall = dd->wall != 0;
+  const Real *pv = static_cast<const Real *>(dd->prev[parity]);
+  const Consts<double> &K = dd->cd;
+  double Jx = 0.0, Jy = 0.0;
+  for (int i = 0; i < M; ++i) {
+    double gx, gy;
+    grad9(C + (int64_t)i * n, x, y, nx, ny, wall, gx, gy);
+    Jx += K.Jc[i] * gx;
+    Jy += K.Jc[i] * gy;
+  }
+  const double ux = (double)pv[at(dd, 2, M, y, x)], uy = (double)pv[at(dd, 2, M + 1, y, x)];
+  q[id] = Jx * ux;
+  q[n + id] = Jy * ux;
+  q[2 * n + id] = Jx * uy;
+  q[3 * n + id] = Jy * uy;
+}
+
+// u (eq:N22_1) and p (eq:N23) in FP64; with q non-null the force also
+// carries -div(J~ u) of Remark 1, component a = sum_b d_b q(b, a)
 template <typename Real>
 __global__ void k_macro_up(const DomDesc *dd, int M, int parity, const double *phi,
-                           const double *rho, const double *C, double *uout, double *pout) {
+                           const double *rho, const double *C, const double *q, double *uout,
+                           double *pout) {
   const int nx = dd->nx, ny = dd->ny, pitch = dd->pitch;
   const int64_t n = (int64_t)nx * ny;
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -231,7 +260,7 @@ __global__ void k_macro_up(const DomDesc *dd, int M, int parity, const double *p
   double Fx = 0.0, Fy = 0.0, grx = 0.0, gry = 0.0;
   for (int i = 0; i < M; ++i) {
     double gx, gy;
-    if (dd->grad == kGradMixed)
+    if (dd->scheme == kSchemeMixed)
       grad_mixed(phi + (int64_t)i * n, x, y, nx, ny, wall, gx, gy);
     else
       grad9(phi + (int64_t)i * n, x, y, nx, ny, wall, gx, gy);
@@ -244,6 +273,15 @@ __global__ void k_macro_up(const DomDesc *dd, int M, int parity, const double *p
   const double r = rho[id];
   Fx += r * K.gx;
   Fy += r * K.gy;
+  if (q) {
+    double axx, axy, ayx, ayy, bxx, bxy, byx, byy;
+    grad9(q, x, y, nx, ny, wall, axx, axy);
+    grad9(q + n, x, y, nx, ny, wall, ayx, ayy);
+    grad9(q + 2 * n, x, y, nx, ny, wall, bxx, bxy);
+    grad9(q + 3 * n, x, y, nx, ny, wall, byx, byy);
+    Fx -= axx + ayy;
+    Fy -= bxx + byy;
+  }
   double gk[9];
   gk[0] = 0.0;
   for (int k = 1; k < 9; ++k) {
@@ -414,7 +452,7 @@ hipError_t launch_init(const DomDesc *dd_dev, const DomDesc &dd, int precision,
 
 hipError_t launch_macro(const DomDesc *dd_dev, const DomDesc &dd, int precision, int parity,
                         double *phi, double *rho, double *C, double *c_out, double *u_out,
-                        double *p_out, hipStream_t st) {
+                        double *p_out, double *q, hipStream_t st) {
   const int M = dd.N - 1;
   const int64_t n = (int64_t)dd.nx * dd.ny;
   const int nb = blocks_for(n);
@@ -426,12 +464,22 @@ hipError_t launch_macro(const DomDesc *dd_dev, const DomDesc &dd, int precision,
                        phi, rho, c_out);
   if (!u_out && !p_out) return hipGetLastError();
   hipLaunchKernelGGL(k_chem, dim3(nb), dim3(kThreads), 0, st, dd_dev, M, phi, C);
+  const double *qq = dd.scheme == kSchemeRemark1 ? q : nullptr;
+  if (dd.scheme == kSchemeRemark1) {
+    if (!q) return hipErrorInvalidValue;
+    if (precision == 64)
+      hipLaunchKernelGGL(k_macro_q<double>, dim3(nb), dim3(kThreads), 0, st, dd_dev, M, parity,
+                         C, q);
+    else
+      hipLaunchKernelGGL(k_macro_q<float>, dim3(nb), dim3(kThreads), 0, st, dd_dev, M, parity,
+                         C, q);
+  }
   if (precision == 64)
     hipLaunchKernelGGL(k_macro_up<double>, dim3(nb), dim3(kThreads), 0, st, dd_dev, M, parity,
-                       phi, rho, C, u_out, p_out);
+                       phi, rho, C, qq, u_out, p_out);
   else
     hipLaunchKernelGGL(k_macro_up<float>, dim3(nb), dim3(kThreads), 0, st, dd_dev, M, parity,
-                       phi, rho, C, u_out, p_out);
+                       phi, rho, C, qq, u_out, p_out);
   return hipGetLastError();
 }
 

@@ -34,7 +34,7 @@ struct Layout {
   size_t h[2] = {0, 0}, g[2] = {0, 0}, prev[2] = {0, 0}, state_end = 0;
   size_t desc = 0, strips = 0;
   int nstrips = 0;
-  size_t phi = 0, rho = 0, C = 0, c = 0, u = 0, p = 0;
+  size_t phi = 0, rho = 0, C = 0, c = 0, u = 0, p = 0, q = 0;
   int nblk = 0;
   size_t partials = 0, out = 0;
   size_t total = 0;
@@ -48,7 +48,10 @@ int64_t plane_pad(size_t elem);
 // default padding of every row block of the row-interleaved layout
 constexpr size_t kRowPadBytes = 0;
 int64_t row_pad(size_t elem);
-int resident_step_blocks(int N, int precision, int grad);
+// step-kernel scheme (kSchemeCentral / kSchemeMixed / kSchemeRemark1) of a
+// validated parameter set
+int step_scheme(const nplbm_params *p);
+int resident_step_blocks(int N, int precision, int scheme);
 void build_strips(int nx, int ny, int dom, const StepGeom &geom, std::vector<StripDesc> &out,
                   int target = 0);
 void xcd_order(std::vector<StripDesc> &s);

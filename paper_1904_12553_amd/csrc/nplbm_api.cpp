@@ -47,7 +47,7 @@ int launch_one_step(nplbm_domain *d) {
   a.strips = d->strips_dev;
   a.doms = d->desc_dev;
   a.substep = (int)(d->t & 1);
-  hipError_t e = launch_step(d->p.N, d->p.precision, d->p.grad_scheme, d->geom.bw, a,
+  hipError_t e = launch_step(d->p.N, d->p.precision, step_scheme(&d->p), d->geom.bw, a,
                              d->nstrips, d->stream);
   if (e != hipSuccess) return hip_fail(e, "step launch");
   d->t += 1;
@@ -67,7 +67,7 @@ int capture_graph(nplbm_domain *d) {
   hipError_t le = hipSuccess;
   for (int s = 0; s < kGraphSteps && le == hipSuccess; ++s) {
     a.substep = s & 1;
-    le = launch_step(d->p.N, d->p.precision, d->p.grad_scheme, d->geom.bw, a, d->nstrips,
+    le = launch_step(d->p.N, d->p.precision, step_scheme(&d->p), d->geom.bw, a, d->nstrips,
                      d->stream);
   }
   e = hipStreamEndCapture(d->stream, &g);
@@ -91,7 +91,8 @@ int readback(nplbm_domain *d, bool want_up) {
   hipError_t e = launch_macro(d->desc_dev, d->desc, d->p.precision, par, dptr(d, d->L.phi),
                               dptr(d, d->L.rho), dptr(d, d->L.C), dptr(d, d->L.c),
                               want_up ? dptr(d, d->L.u) : nullptr,
-                              want_up ? dptr(d, d->L.p) : nullptr, d->stream);
+                              want_up ? dptr(d, d->L.p) : nullptr,
+                              d->L.q ? dptr(d, d->L.q) : nullptr, d->stream);
   if (e != hipSuccess) return hip_fail(e, "macro launch");
   return NPLBM_OK;
 }
@@ -203,12 +204,12 @@ int nplbm_create(const nplbm_params *p, void *stream, void *device_mem, size_t d
   D.N = N;
   D.parity0 = 0;
   D.steps_left = INT_MAX;
-  D.grad = p->grad_scheme;
+  D.scheme = step_scheme(p);
   D.cd = d->d.cd;
   D.cf = d->d.cf;
   d->desc_dev = reinterpret_cast<DomDesc *>(d->base + d->L.desc);
   std::vector<StripDesc> strips;
-  d->geom = step_geom(p->N, p->precision, p->grad_scheme);
+  d->geom = step_geom(p->N, p->precision, step_scheme(p));
   build_strips(p->nx, p->ny, 0, d->geom, strips, single_domain_target(p));
   xcd_order(strips);
   if ((int)strips.size() > d->L.nstrips) {

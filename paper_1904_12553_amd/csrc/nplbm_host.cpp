@@ -99,8 +99,17 @@ int derive(const nplbm_params *p, Derived &d) {
     return fail(NPLBM_EINVAL, "domain larger than 2^30 nodes");
   if (p->precision != 32 && p->precision != 64)
     return fail(NPLBM_EINVAL, "precision must be 32 or 64");
+  // the step kernel addresses one row block of a state group (all its
+  // planes of one lattice row) with 32-bit byte offsets below 2^31
+  if ((int64_t)9 * (N - 1) * (((int64_t)p->nx + 31) & ~(int64_t)31) * (p->precision / 8) >=
+      (int64_t)1 << 31)
+    return fail(NPLBM_EINVAL, "nx=%d too large: a row block would exceed 2^31 bytes", p->nx);
   if (p->grad_scheme != kGradCentral && p->grad_scheme != kGradMixed)
     return fail(NPLBM_EINVAL, "grad_scheme must be 0 (eq:N31a) or 1 (eq:N40)");
+  if (p->force_form != 0 && p->force_form != 1)
+    return fail(NPLBM_EINVAL, "force_form must be 0 (eq:N20_1) or 1 (Remark 1)");
+  if (p->force_form == 1 && p->grad_scheme != kGradCentral)
+    return fail(NPLBM_EINVAL, "force_form 1 is built with grad_scheme 0 only");
   if (p->wall_y != 0 && p->wall_y != 1) return fail(NPLBM_EINVAL, "wall_y must be 0 or 1");
   if (!p->sigma || !p->rho || !p->mu || !p->mobility || !p->tau_phi)
     return fail(NPLBM_EINVAL, "a parameter array is NULL");
@@ -316,7 +325,12 @@ int64_t row_pad(size_t elem) {
 // configuration (two 8-wave FP32 workgroups at N = 3) measured 4 points of
 // the HBM roofline slower than one: twice as many concurrent row streams and
 // half-height strips, for no gain in bytes in flight.
-int resident_step_blocks(int N, int precision, int grad) {
+int step_scheme(const nplbm_params *p) {
+  if (p->grad_scheme == kGradMixed) return kSchemeMixed;
+  return p->force_form == 1 ? kSchemeRemark1 : kSchemeCentral;
+}
+
+int resident_step_blocks(int N, int precision, int scheme) {
   static int cus = -1;
   if (cus < 0) {
     int dev = 0;
@@ -326,8 +340,8 @@ int resident_step_blocks(int N, int precision, int grad) {
     else
       cus = 0;
   }
-  const int bw = step_geom(N, precision, grad).bw;
-  const int per = step_blocks_per_cu(N, precision, grad, bw);
+  const int bw = step_geom(N, precision, scheme).bw;
+  const int per = step_blocks_per_cu(N, precision, scheme, bw);
   const int cap = std::max(1, 8 / std::max(1, bw * kRows / 64));
   return cus > 0 && per > 0 ? cus * std::min(per, cap) : 0;
 }
@@ -339,7 +353,7 @@ int single_domain_target(const nplbm_params *p) {
     const int t = std::atoi(env);
     if (t > 0) return t;
   }
-  const int r = resident_step_blocks(p->N, p->precision, p->grad_scheme);
+  const int r = resident_step_blocks(p->N, p->precision, step_scheme(p));
   return r > 0 ? r : 2048;
 }
 
@@ -384,6 +398,8 @@ Layout plan_layout(const nplbm_params *p) {
   L.c = take((size_t)N * n * 8);
   L.u = take(2 * n * 8);
   L.p = take(n * 8);
+  // the products J~_b u_a of the Remark 1 force, for the read-back
+  L.q = p->force_form == 1 ? take(4 * n * 8) : 0;
   L.nblk = diag_blocks((int64_t)n);
   L.partials = take((size_t)L.nblk * (kMaxN + 2) * 8);
   L.out = take((kMaxN + 2) * 8);
@@ -391,21 +407,22 @@ Layout plan_layout(const nplbm_params *p) {
   return L;
 }
 
-// Strip geometry of the step kernel for a precision and gradient scheme.
+// Strip geometry of the step kernel for a precision and scheme.
 // Interior widths are multiples of one 128-byte cache line of state values
 // (32 floats or 16 doubles), so no line is written by two workgroups; rows
 // of 256 threads for FP32 and 64 for FP64 measured fastest on gfx950.  The
-// halo is 2 columns for the central gradients and 3 for the two-hop ones.
-StepGeom step_geom(int N, int precision, int grad) {
+// halo is 2 columns for the central gradients and 3 for the two-hop ones
+// (eq:N40, or the divergence of Remark 1 taken of a product of gradients).
+StepGeom step_geom(int N, int precision, int scheme) {
   StepGeom g;
-  g.halo = grad == kGradMixed ? 3 : 2;
+  g.halo = scheme == kSchemeCentral ? 2 : 3;
   const int unit = precision == 64 ? 16 : 32;
   g.bw = precision == 64 ? 64 : 256;
   if (const char *e = std::getenv("NPLBM_BW")) {
     const int b = std::atoi(e);
     g.bw = (b == 128 || b == 256) ? b : 64;
   }
-  g.bw = std::min(g.bw, step_max_bw(N, precision, grad));
+  g.bw = std::min(g.bw, step_max_bw(N, precision, scheme));
   g.tx = ((g.bw - 2 * g.halo) / unit) * unit;
   if (const char *e = std::getenv("NPLBM_TX")) g.tx = std::atoi(e);
   if (g.tx < 8) g.tx = 8;

@@ -20,15 +20,21 @@ struct StepGeom {
   int unit;  // strip widths are multiples of this many columns (one cache line)
   int halo;  // halo columns on each side
 };
-// Gradient schemes: central isotropic (eq:N31a) or the isotropic mixed scheme
-// of eq:N40 (sign of its two-hop term read as negative).
+// Gradient schemes (nplbm_params.grad_scheme): central isotropic (eq:N31a)
+// or the isotropic mixed scheme of eq:N40 (sign of its two-hop term read as
+// negative).
 constexpr int kGradCentral = 0;
 constexpr int kGradMixed = 1;
-// Geometry used for N phases at a precision (32 / 64) and gradient scheme;
+// Step-kernel schemes: central stencils with eq:N20_1, mixed stencils with
+// eq:N20_1, central stencils with the force distribution of Remark 1.
+constexpr int kSchemeCentral = 0;
+constexpr int kSchemeMixed = 1;
+constexpr int kSchemeRemark1 = 2;
+// Geometry used for N phases at a precision (32 / 64) and scheme;
 // NPLBM_BW and NPLBM_TX override.
-StepGeom step_geom(int N, int precision, int grad);
-// widest row width the step kernel is built with for (N, precision, grad)
-int step_max_bw(int N, int precision, int grad);
+StepGeom step_geom(int N, int precision, int scheme);
+// widest row width the step kernel is built with for (N, precision, scheme)
+int step_max_bw(int N, int precision, int scheme);
 
 // Per-domain constants, folded on the host from the paper's closure so that
 // every per-node quantity is an affine map or a short dot product:
@@ -73,7 +79,7 @@ struct DomDesc {
   int32_t N;
   int32_t parity0;   // buffer holding the current state at substep 0
   int32_t steps_left;  // substeps >= steps_left do nothing
-  int32_t grad;        // gradient scheme (kGradCentral / kGradMixed)
+  int32_t scheme;      // step-kernel scheme (kSchemeCentral / Mixed / Remark1)
   Consts<double> cd;
   Consts<float> cf;
 };
@@ -97,17 +103,20 @@ struct StepArgs {
 };
 
 // Launchers (defined in the .hip files).  All are asynchronous on `st`.
-hipError_t launch_step(int N, int precision, int grad, int bw, const StepArgs &a,
+hipError_t launch_step(int N, int precision, int scheme, int bw, const StepArgs &a,
                        int nblocks, hipStream_t st);
 // resident step-kernel workgroups per compute unit (0 if unknown)
-int step_blocks_per_cu(int N, int precision, int grad, int bw);
-// the same for one gradient scheme (one translation unit each)
+int step_blocks_per_cu(int N, int precision, int scheme, int bw);
+// the same for one scheme (one translation unit each)
 hipError_t launch_step_central(int N, int precision, int bw, const StepArgs &a, int nblocks,
                                hipStream_t st);
 hipError_t launch_step_mixed(int N, int precision, int bw, const StepArgs &a, int nblocks,
                              hipStream_t st);
+hipError_t launch_step_remark1(int N, int precision, int bw, const StepArgs &a, int nblocks,
+                               hipStream_t st);
 int step_blocks_per_cu_central(int N, int precision, int bw);
 int step_blocks_per_cu_mixed(int N, int precision, int bw);
+int step_blocks_per_cu_remark1(int N, int precision, int bw);
 
 // Initialisation: phi (double, (N-1) planes of nx*ny) is computed from c,
 // then C from phi, then h^eq / g^eq written in pull layout.
@@ -119,10 +128,11 @@ hipError_t launch_init(const DomDesc *dd_dev, const DomDesc &dd, int precision,
 
 // Macroscopic fields in FP64 from the current state: phi (N-1), c (N), rho,
 // C (N-1), u (2), p.  Any output plane pointer group may be null.
-// Dense planes (nx*ny); u/p need the C scratch.
+// Dense planes (nx*ny); u/p need the C scratch, and with the Remark 1
+// scheme 4 more planes q for the products J~_b u_a.
 hipError_t launch_macro(const DomDesc *dd_dev, const DomDesc &dd, int precision, int parity,
                         double *phi, double *rho, double *C, double *c_out, double *u_out,
-                        double *p_out, hipStream_t st);
+                        double *p_out, double *q, hipStream_t st);
 
 // FP64 reductions over the c fields (N planes): per-phase sums, max
 // |sum c - 1|, non-finite count.  partials must hold nblk*(N+2) doubles.

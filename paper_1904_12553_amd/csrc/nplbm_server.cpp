@@ -71,7 +71,7 @@ struct nplbm_server {
   StripDesc *strips_dev = nullptr;
   size_t strips_cap = 0;
   struct Group {
-    int N, precision, grad;
+    int N, precision, scheme;
     size_t off, count;
   };
   std::vector<Group> groups;
@@ -129,7 +129,7 @@ int admit(nplbm_server *s, Req *r) {
   D.N = r->p.N;
   D.parity0 = 0;
   D.steps_left = INT_MAX;
-  D.grad = r->p.grad_scheme;
+  D.scheme = step_scheme(&r->p);
   D.cd = r->d.cd;
   D.cf = r->d.cf;
   const size_t n = (size_t)r->p.nx * r->p.ny;
@@ -159,8 +159,8 @@ int admit(nplbm_server *s, Req *r) {
   return NPLBM_OK;
 }
 
-// Rebuild the packed strip tables (one per (N, precision, gradient scheme)
-// group) and recapture the quantum graph.
+// Rebuild the packed strip tables (one per (N, precision, step-kernel
+// scheme) group) and recapture the quantum graph.
 int rebuild(nplbm_server *s) {
   if (s->graph) {
     (void)hipGraphExecDestroy(s->graph);
@@ -168,18 +168,18 @@ int rebuild(nplbm_server *s) {
   }
   s->groups.clear();
   std::vector<StripDesc> all;
-  for (int grad : {kGradCentral, kGradMixed})
+  for (int sch : {kSchemeCentral, kSchemeMixed, kSchemeRemark1})
     for (int prec : {32, 64})
       for (int N = 2; N <= kMaxN; ++N) {
         std::vector<StripDesc> g;
         for (int slot = 0; slot < s->max_slots; ++slot) {
           Req *r = s->slots[slot];
-          if (!r || r->p.N != N || r->p.precision != prec || r->p.grad_scheme != grad) continue;
-          build_strips(r->p.nx, r->p.ny, slot, step_geom(N, prec, grad), g);
+          if (!r || r->p.N != N || r->p.precision != prec || step_scheme(&r->p) != sch) continue;
+          build_strips(r->p.nx, r->p.ny, slot, step_geom(N, prec, sch), g);
         }
         if (g.empty()) continue;
         xcd_order(g);
-        s->groups.push_back({N, prec, grad, all.size(), g.size()});
+        s->groups.push_back({N, prec, sch, all.size(), g.size()});
         all.insert(all.end(), g.begin(), g.end());
       }
   s->dirty = false;
@@ -209,8 +209,8 @@ int rebuild(nplbm_server *s) {
       a.strips = s->strips_dev + gr.off;
       a.doms = s->descs_dev;
       a.substep = q;
-      le = launch_step(gr.N, gr.precision, gr.grad, step_geom(gr.N, gr.precision, gr.grad).bw, a,
-                       (int)gr.count, s->stream);
+      le = launch_step(gr.N, gr.precision, gr.scheme,
+                       step_geom(gr.N, gr.precision, gr.scheme).bw, a, (int)gr.count, s->stream);
       if (le != hipSuccess) break;
     }
   e = hipStreamEndCapture(s->stream, &g);
@@ -238,7 +238,7 @@ int retire(nplbm_server *s, Req *r) {
   auto dp = [&](size_t off) { return reinterpret_cast<double *>(r->base + off); };
   hipError_t e = launch_macro(s->descs_dev + r->slot, D, r->p.precision, par, dp(r->L.phi),
                               dp(r->L.rho), dp(r->L.C), dp(r->L.c), dp(r->L.u), dp(r->L.p),
-                              s->stream);
+                              r->L.q ? dp(r->L.q) : nullptr, s->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(r->c_out.data(), dp(r->L.c), r->c_out.size() * 8, hipMemcpyDeviceToHost,
                        s->stream);

@@ -19,13 +19,20 @@
 //            CH populations this thread pulled kLag rows earlier (kept in
 //            registers), then store.
 //
-// Two gradient schemes are built (template parameter kGS):
-//   - central (eq:N31a): one-hop stencils; 2-column halo, C needed one row
-//     ahead of the collision, so kLag = 2;
-//   - mixed (eq:N40 with its two-hop term read as negative): two-hop
+// Three schemes are built (template parameter kGS):
+//   - 0, central (eq:N31a): one-hop stencils; 2-column halo, C needed one
+//     row ahead of the collision, so kLag = 2;
+//   - 1, mixed (eq:N40 with its two-hop term read as negative): two-hop
 //     stencils; 3-column halo, C needed two rows ahead, phi three, and the
 //     lag must be even (a row is pulled and collided by the same wave), so
-//     kLag = 4 and a third register set holds the pulls in between.
+//     kLag = 4 and a third register set holds the pulls in between;
+//   - 2, central stencils with the force distribution of Remark 1 (Sec.
+//     3.1): G_k loses its J~ u / (tau_g - 1/2) term and F gains
+//     -div(J~ u), component a = sum_b d_b (J~_b u_a) with u of the previous
+//     step (the stored u of eq:N27).  J~ is needed one row and one column
+//     around the collision node, so C two rows ahead and phi three, as for
+//     the mixed scheme; a stage J between stages B and C forms the products
+//     J~_b u_a into a fourth LDS ring, behind a third barrier.
 //
 // So every population is read from HBM once and written once per step; the
 // only re-reads are the x-halo and a short row ramp at the strip start,
@@ -117,6 +124,7 @@ template <int M, typename Real>
 struct Pulled {
   Real h[M][9];  // h[i][0] is the stored deviation of h_0, h[i][k>=1] streamed in
   Real hi[M];    // stored phi_i of the previous step
+  Real pu[2];    // stored u of the previous step (Remark 1 scheme only)
 };
 // NS populations and previous velocity of the row being collided, loaded
 // one stage before use.
@@ -139,6 +147,12 @@ template <>
 struct Scheme<1> {
   static constexpr int kPR = 10, kCR = 8, kHalo = 3, kRamp = 4, kLag = 4;
 };
+template <>
+struct Scheme<2> {
+  static constexpr int kPR = 10, kCR = 8, kHalo = 3, kRamp = 4, kLag = 4;
+};
+// rings of the Remark 1 scheme: the products J~_b u_a and the previous u
+constexpr int kQR = 8, kUR = 4;
 // slot of march index m (m >= -16 R) in a ring of R rows
 template <int R>
 __device__ __forceinline__ int ring(int m) {
@@ -150,6 +164,8 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   constexpr int M = N - 1;
   using S = Scheme<kGS>;
   constexpr int kPR = S::kPR, kCR = S::kCR, kHalo = S::kHalo;
+  constexpr bool kTwoHop = kGS == 1;  // eq:N40 first derivatives
+  constexpr bool kR1 = kGS == 2;      // Remark 1 force distribution
   const NPL_CONST StripDesc *sp = (const NPL_CONST StripDesc *)a.strips + blockIdx.x;
   StripDesc sd;
   sd.dom = sp->dom;
@@ -177,6 +193,8 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
 
   __shared__ Real sphi[kPR][M][kBW];
   __shared__ Real sC[kCR][M][kBW];
+  __shared__ Real sQ[kR1 ? kQR : 1][4][kBW];  // J~_x u_x, J~_y u_x, J~_x u_y, J~_y u_y
+  __shared__ Real sU[kR1 ? kUR : 1][2][kBW];  // previous u
 
   const int lane = threadIdx.x & (kBW - 1);
   // the row handled by this wave (uniform; said explicitly so every row,
@@ -260,6 +278,10 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
     const Rsrc rp = row_rsrc(pvs, rbp, yp);
 #pragma unroll
     for (int i = 0; i < M; ++i) P.hi[i] = bld<Real>(rp, xcu, (uint32_t)i * pb);
+    if constexpr (kR1) {
+      P.pu[0] = bld<Real>(rp, xcu, (uint32_t)M * pb);
+      P.pu[1] = bld<Real>(rp, xcu, (uint32_t)(M + 1) * pb);
+    }
   };
   // ---- pull the NS populations and stored u of march index m ----
   auto pull_ns = [&](int m, PulledNS<Real> &Q) {
@@ -285,6 +307,10 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
     const int slot = ring<kPR>(mA);
 #pragma unroll
     for (int i = 0; i < M; ++i) sphi[slot][i][lane] = cur.hi[i] + lo_sum(cur.h[i]);  // eq:N28
+    if constexpr (kR1) {
+      sU[ring<kUR>(mA)][0][lane] = cur.pu[0];
+      sU[ring<kUR>(mA)][1][lane] = cur.pu[1];
+    }
   };
 
   // ---- stage B: chemical potentials for march index mB -> LDS ----
@@ -297,7 +323,7 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   auto stageB = [&](int mB) {
     if (lane < 1 || lane > ncol + 2 * kHalo - 2) return;
     int me = mB;
-    if (kGS == 0 && wall) {
+    if (!kTwoHop && wall) {
       const int r = row_of(mB);
       if (r < 0) me = mB + dir;          // ghost below row 0: C(-1) = C(0)
       else if (r >= ny) me = mB - dir;   // ghost above row ny-1
@@ -336,6 +362,38 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
     }
   };
 
+  // ---- stage J (Remark 1 scheme): J~ and the products J~_b u_a ----
+  // J~ (eq:N18 line 4) from the eq:N31a gradients of C, on the interior
+  // columns and one either side, times the stored previous u.  Ghost rows
+  // beyond a wall are not evaluated: stage C reads the mirrored row, the
+  // same values (the ghost of a field is its mirror image).
+  auto stageJ = [&](int mJ) {
+    if (lane < 2 || lane > ncol + 2 * kHalo - 3) return;
+    if (wall) {
+      const int r = row_of(mJ);
+      if (r < 0 || r >= ny) return;
+    }
+    const int q0 = ring<kCR>(mJ), qN = ring<kCR>(mJ + dir), qS = ring<kCR>(mJ - dir);
+    Real Jx = Real(0), Jy = Real(0);
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      const Real e = sC[q0][i][lane + 1], w = sC[q0][i][lane - 1];
+      const Real n = sC[qN][i][lane], s = sC[qS][i][lane];
+      const Real ne = sC[qN][i][lane + 1], nw = sC[qN][i][lane - 1];
+      const Real se = sC[qS][i][lane + 1], sw = sC[qS][i][lane - 1];
+      const Real gx = (Real(4) * (e - w) + ((ne - nw) + (se - sw))) * (Real(1) / Real(12));
+      const Real gy = (Real(4) * (n - s) + ((ne + nw) - (se + sw))) * (Real(1) / Real(12));
+      Jx += K.Jc[i] * gx;
+      Jy += K.Jc[i] * gy;
+    }
+    const int su = ring<kUR>(mJ), sq = ring<kQR>(mJ);
+    const Real ux = sU[su][0][lane], uy = sU[su][1][lane];
+    sQ[sq][0][lane] = Jx * ux;
+    sQ[sq][1][lane] = Jy * ux;
+    sQ[sq][2][lane] = Jx * uy;
+    sQ[sq][3][lane] = Jy * uy;
+  };
+
   // ---- stage C: collide march index mC with what was pulled for it ----
   auto stageC = [&](int mC, const Pulled<M, Real> &P, const PulledNS<Real> &Q) {
     if (!interior || mC < 0 || mC >= H) return;
@@ -343,7 +401,7 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
     const int p0 = ring<kPR>(mC), pN = ring<kPR>(mC + dir), pS = ring<kPR>(mC - dir);
     const int q0 = ring<kCR>(mC), qN = ring<kCR>(mC + dir), qS = ring<kCR>(mC - dir);
     Real phi[M], Cv[M], gpx[M], gpy[M], gCx[M], gCy[M];
-    if constexpr (kGS == 0) {
+    if constexpr (!kTwoHop) {
       // eq:N31a on D2Q9: d/dx = [4 (E - W) + (NE - NW + SE - SW)] / 12
       auto grad = [&](const Real (*f)[M][kBW], int r0, int rN, int rS, int i, Real &gx,
                       Real &gy) {
@@ -359,7 +417,7 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
         phi[i] = sphi[p0][i][lane];
         Cv[i] = sC[q0][i][lane];
         grad(sphi, p0, pN, pS, i, gpx[i], gpy[i]);
-        grad(sC, q0, qN, qS, i, gCx[i], gCy[i]);
+        if constexpr (!kR1) grad(sC, q0, qN, qS, i, gCx[i], gCy[i]);
       }
     } else {
       // eq:N40 summed over the D2Q9 directions.  Per direction c the
@@ -405,11 +463,39 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
       gry += K.rA[i] * gpy[i];
       Fx += Cv[i] * gpx[i];
       Fy += Cv[i] * gpy[i];
-      Jx += K.Jc[i] * gCx[i];
-      Jy += K.Jc[i] * gCy[i];
+      if constexpr (!kR1) {
+        Jx += K.Jc[i] * gCx[i];
+        Jy += K.Jc[i] * gCy[i];
+      }
     }
     Fx += rho * K.gx;
     Fy += rho * K.gy;
+    if constexpr (kR1) {
+      // Remark 1: F -= div(J~ u), (div)_x = d_x q0 + d_y q1,
+      // (div)_y = d_x q2 + d_y q3, eq:N31a on the product ring; a row
+      // beyond a wall is its mirror, the collision row itself
+      auto ghost = [&](int m) {
+        const int r = row_of(m);
+        return wall && (r < 0 || r >= ny);
+      };
+      const int s0 = ring<kQR>(mC);
+      const int sN = ghost(mC + dir) ? s0 : ring<kQR>(mC + dir);
+      const int sS = ghost(mC - dir) ? s0 : ring<kQR>(mC - dir);
+      auto ddx = [&](int c) {
+        return (Real(4) * (sQ[s0][c][lane + 1] - sQ[s0][c][lane - 1]) +
+                ((sQ[sN][c][lane + 1] - sQ[sN][c][lane - 1]) +
+                 (sQ[sS][c][lane + 1] - sQ[sS][c][lane - 1]))) *
+               (Real(1) / Real(12));
+      };
+      auto ddy = [&](int c) {
+        return (Real(4) * (sQ[sN][c][lane] - sQ[sS][c][lane]) +
+                ((sQ[sN][c][lane + 1] + sQ[sN][c][lane - 1]) -
+                 (sQ[sS][c][lane + 1] + sQ[sS][c][lane - 1]))) *
+               (Real(1) / Real(12));
+      };
+      Fx -= ddx(0) + ddy(1);
+      Fy -= ddx(2) + ddy(3);
+    }
     Real itau, srcg, theta;
     if (K.const_tau) {
       itau = K.itau_g;
@@ -442,7 +528,7 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
     const Real Ju = Jx * ux + Jy * uy;
     // isotropic part of eq:N20_1: u.grad(rho) - tr(T) / (2 c_s^2)
     const Real gbase =
-        udr - Real(1.5) * (Real(2) * uF + Real(2) / Real(3) * udr + theta * Ju);
+        udr - Real(1.5) * (Real(2) * uF + Real(2) / Real(3) * udr + (kR1 ? Real(0) : theta * Ju));
     const Rsrc wh = row_rsrc(hd, rbh, yp), wg = row_rsrc(gd, rbg, yp),
                wp = row_rsrc(pvd, rbp, yp);
 #pragma unroll
@@ -457,7 +543,7 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
           w * (Real(3) * p + rho * (Real(3) * cu + Real(4.5) * cu * cu - Real(1.5) * usq));
       const Real G =
           w * (gbase + Real(3) * cF +
-               Real(4.5) * cu * (Real(2) * cF + Real(2) / Real(3) * cr + theta * cJ));
+               Real(4.5) * cu * (Real(2) * cF + Real(2) / Real(3) * cr + (kR1 ? Real(0) : theta * cJ)));
       bst<Real>(wg, xcu, (uint32_t)(k - 1) * pb, g[k] - itau * (g[k] - geq) + srcg * G);
     }
     // CH collisions
@@ -504,15 +590,18 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   //    mA, next = mA + 2, held = mA - 2);
   //  - central otherwise: two sets (cur, held = mA - 2); three would halve
   //    the occupancy or spill;
-  //  - mixed, N <= 4: three sets (cur, mA - 2, mA - 4);
-  //  - mixed, N >= 5: three sets would spill or leave one wave per SIMD, so
+  //  - mixed and Remark 1, N <= 4: three sets (cur, mA - 2, mA - 4); the
+  //    Remark 1 scheme runs stage J on rows mA - 2 behind a third barrier
+  //    before the collision;
+  //  - mixed and Remark 1, N >= 5: three sets would spill or leave one wave
+  //    per SIMD, so
   //    the collision row's CH populations are pulled a second time (from
   //    L2 / MALL, 2 iterations after the first pull) and one set suffices.
   //    Measured on the 2048^2 N = 5 workload: 45% of the HBM roofline in
   //    FP32 against 37% with three sets (the re-read costs the central
   //    scheme 13 points, so it is used only here).
   constexpr int kRamp = S::kRamp, kLag = S::kLag;
-  constexpr bool kRepull = kGS == 1 && N >= 5;
+  constexpr bool kRepull = kGS != 0 && N >= 5;
   const int J = (H + kRamp + kLag + 1) / 2;
   PulledNS<Real> ns;
   constexpr bool kPipeline = kGS == 0 && sizeof(Real) == 4 && N <= 5;
@@ -529,9 +618,13 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
       pull_ch(mA - kLag, buf);
       stageB(mA - 1);
       __syncthreads();
+      if constexpr (kR1) {
+        stageJ(mA - 2);
+        __syncthreads();
+      }
       stageC(mA - kLag, buf, ns);
     }
-  } else if constexpr (kGS == 1) {
+  } else if constexpr (kGS != 0) {
     Pulled<M, Real> bufA, bufB, bufC;
     auto iteration = [&](int j, Pulled<M, Real> &cur, const Pulled<M, Real> &held) {
       const int mA = 2 * j - kRamp + ry;
@@ -541,6 +634,10 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
       pull_ns(mA - kLag, ns);
       stageB(mA - 1);
       __syncthreads();
+      if constexpr (kR1) {
+        stageJ(mA - 2);
+        __syncthreads();
+      }
       stageC(mA - kLag, held, ns);
     };
     for (int j = 0; j < J; j += 3) {  // j is uniform over the block
@@ -586,20 +683,25 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   }
 }
 
-// This translation unit instantiates the kernel for one gradient scheme,
-// NPL_GS (0 central, 1 mixed; step_kernel_mixed.hip builds the latter), so
-// the two sets of instantiations compile in parallel.
+// This translation unit instantiates the kernel for one scheme, NPL_GS (0
+// central, 1 mixed, 2 Remark 1; step_kernel_mixed.hip and
+// step_kernel_remark1.hip build the last two), so the three sets of
+// instantiations compile in parallel.
 #ifndef NPL_GS
 #define NPL_GS 0
 #endif
 
-// LDS of one workgroup: the phi and C rings of (N-1) x BW values
+// LDS of one workgroup: the phi and C rings of (N-1) x BW values, plus the
+// product and velocity rings of the Remark 1 scheme
 constexpr int lds_bytes(int N, int bytes, int bw, int gs) {
-  return (gs ? Scheme<1>::kPR + Scheme<1>::kCR : Scheme<0>::kPR + Scheme<0>::kCR) * (N - 1) *
+  return ((gs == 1 ? Scheme<1>::kPR + Scheme<1>::kCR
+                   : (gs == 2 ? Scheme<2>::kPR + Scheme<2>::kCR : Scheme<0>::kPR + Scheme<0>::kCR)) *
+              (N - 1) +
+          (gs == 2 ? 4 * kQR + 2 * kUR : 0)) *
          bw * bytes;
 }
 // LDS budget of a workgroup: 64 KiB for the central scheme; 80 KiB for the
-// mixed one (gfx950 has 160 KiB per CU, so two such workgroups still fit)
+// others (gfx950 has 160 KiB per CU, so two such workgroups still fit)
 constexpr int lds_budget(int gs) { return gs ? 80 * 1024 : 64 * 1024; }
 // the widest row a (N, precision, scheme) is built for
 constexpr int max_bw(int N, int bytes, int gs) {
@@ -609,8 +711,8 @@ constexpr int max_bw(int N, int bytes, int gs) {
 }
 
 #if NPL_GS == 0
-int step_max_bw(int N, int precision, int grad) {
-  return max_bw(N, precision == 64 ? 8 : 4, grad == kGradMixed ? 1 : 0);
+int step_max_bw(int N, int precision, int scheme) {
+  return max_bw(N, precision == 64 ? 8 : 4, scheme);
 }
 #endif
 
@@ -667,8 +769,10 @@ int occ_n(int precision, int bw) {
 
 #if NPL_GS == 0
 #define NPL_SCHEME_FN(name) name##_central
-#else
+#elif NPL_GS == 1
 #define NPL_SCHEME_FN(name) name##_mixed
+#else
+#define NPL_SCHEME_FN(name) name##_remark1
 #endif
 
 int NPL_SCHEME_FN(step_blocks_per_cu)(int N, int precision, int bw) {
@@ -700,15 +804,17 @@ hipError_t NPL_SCHEME_FN(launch_step)(int N, int precision, int bw, const StepAr
 }
 
 #if NPL_GS == 0
-int step_blocks_per_cu(int N, int precision, int grad, int bw) {
-  return grad == kGradMixed ? step_blocks_per_cu_mixed(N, precision, bw)
-                            : step_blocks_per_cu_central(N, precision, bw);
+int step_blocks_per_cu(int N, int precision, int scheme, int bw) {
+  return scheme == kSchemeMixed     ? step_blocks_per_cu_mixed(N, precision, bw)
+         : scheme == kSchemeRemark1 ? step_blocks_per_cu_remark1(N, precision, bw)
+                                    : step_blocks_per_cu_central(N, precision, bw);
 }
 
-hipError_t launch_step(int N, int precision, int grad, int bw, const StepArgs &a, int nblocks,
+hipError_t launch_step(int N, int precision, int scheme, int bw, const StepArgs &a, int nblocks,
                        hipStream_t st) {
-  return grad == kGradMixed ? launch_step_mixed(N, precision, bw, a, nblocks, st)
-                            : launch_step_central(N, precision, bw, a, nblocks, st);
+  return scheme == kSchemeMixed     ? launch_step_mixed(N, precision, bw, a, nblocks, st)
+         : scheme == kSchemeRemark1 ? launch_step_remark1(N, precision, bw, a, nblocks, st)
+                                    : launch_step_central(N, precision, bw, a, nblocks, st);
 }
 #endif
 

@@ -45,7 +45,7 @@ class NplbmError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("wall_y", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("grad_scheme", ctypes.c_int32),
+                ("grad_scheme", ctypes.c_int32), ("force_form", ctypes.c_int32),
                 ("sigma", ctypes.POINTER(ctypes.c_double)),
                 ("rho", ctypes.POINTER(ctypes.c_double)),
                 ("mu", ctypes.POINTER(ctypes.c_double)),
@@ -117,24 +117,25 @@ def _dp(a: Optional[np.ndarray]):
 
 
 def make_params(N, nx, ny, sigma, rho, mu, mobility=0.1, tau_phi=0.8, W=4.0, wall_y=False,
-                gx=0.0, gy=0.0, precision=64, grad_scheme=0):
+                gx=0.0, gy=0.0, precision=64, grad_scheme=0, force_form=0):
     """Build a Params struct; returns (struct, keepalive arrays)."""
     arr = lambda x, n: np.ascontiguousarray(np.broadcast_to(np.asarray(x, np.float64), (n,)))
     sig = np.ascontiguousarray(np.asarray(sigma, np.float64).reshape(N, N))
     keep = (sig, arr(rho, N), arr(mu, N), arr(mobility, N - 1), arr(tau_phi, N - 1))
     p = Params(N=N, nx=nx, ny=ny, wall_y=int(bool(wall_y)), precision=int(precision),
-               grad_scheme=int(grad_scheme), sigma=_dp(keep[0]), rho=_dp(keep[1]),
+               grad_scheme=int(grad_scheme), force_form=int(force_form), sigma=_dp(keep[0]),
+               rho=_dp(keep[1]),
                mu=_dp(keep[2]), mobility=_dp(keep[3]), tau_phi=_dp(keep[4]),
                interface_width=float(W), gx=float(gx), gy=float(gy))
     return p, keep
 
 
 def validate(N, sigma, rho, mu=None, mobility=0.1, tau_phi=0.8, W=4.0, nx=8, ny=8,
-             grad_scheme=0):
+             grad_scheme=0, force_form=0):
     """Host-only check of a parameter set; returns (lambda, beta2, K)."""
     mu = np.ones(N) if mu is None else mu
     p, keep = make_params(N, nx, ny, sigma, rho, mu, mobility, tau_phi, W,
-                          grad_scheme=grad_scheme)
+                          grad_scheme=grad_scheme, force_form=force_form)
     lam = np.empty((N - 1) * (N - 1))
     b2, K = ctypes.c_double(), ctypes.c_double()
     _check(lib().nplbm_validate(ctypes.byref(p), _dp(lam), ctypes.byref(b2), ctypes.byref(K)))

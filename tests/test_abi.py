@@ -77,6 +77,12 @@ def test_validate_rejects_bad_parameters():
     with pytest.raises(nb.NplbmError) as e:
         nb.validate(3, W.uniform_sigma(3, 1e-3), np.ones(3), grad_scheme=2)
     assert e.value.code == -1
+    # force distributions: 0 (eq:N20_1) and 1 (Remark 1, central stencils only)
+    nb.validate(3, W.uniform_sigma(3, 1e-3), np.ones(3), force_form=1)
+    for kw in (dict(force_form=2), dict(force_form=-1), dict(force_form=1, grad_scheme=1)):
+        with pytest.raises(nb.NplbmError) as e:
+            nb.validate(3, W.uniform_sigma(3, 1e-3), np.ones(3), **kw)
+        assert e.value.code == -1
 
 
 def test_accepts_agrees_with_oracle():

@@ -1,0 +1,116 @@
+"""The total-force distribution of Remark 1 (Sec. 3.1) on the HIP path,
+through the C ABI (force_form=1): G_k without the J~ u / (tau_g - 1/2)
+term and F = -div(J~ u) + F_s + G.  FP64 parity with the oracle's form 1
+(1e-10 max-abs on c, u, p), FP32 against FP64 (1e-5 on c), mass
+conservation, serving next to the other schemes, and a check that the run
+differs from the eq:N20_1 one.  Unequal densities throughout: with equal
+densities J~ vanishes and the two forms coincide."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.accept import oracle_accepts
+from tests.gpu_util import gpu_domain, maxabs, oracle_run
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def _parity(w, steps, precision=64):
+    print(f"case {w.name} {w.nx}x{w.ny} wall={w.wall_y} remark1 steps={steps}", flush=True)
+    o = oracle_run(w, steps, force_form=1)
+    d = gpu_domain(w, precision=precision, force_form=1)
+    d.step(steps)
+    res = [maxabs(a, b) for a, b in zip(d.macro(), o.macro())]
+    d.close()
+    return res
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 5])
+@pytest.mark.parametrize("wall", [False, True])
+def test_remark1_random_parity(N, wall):
+    w = W.random_smooth(N, 130, 70, seed=400 + N + 10 * wall, wall_y=wall,
+                        accept=oracle_accepts)
+    assert max(_parity(w, 40)) < TOL
+
+
+@pytest.mark.parametrize("nx,ny,wall", [(12, 10, False), (9, 4, True), (7, 5, True)])
+def test_remark1_tiny_parity(nx, ny, wall):
+    w = W.random_smooth(3, nx, ny, seed=41 + nx, wall_y=wall, accept=oracle_accepts)
+    assert max(_parity(w, 30)) < TOL
+
+
+def test_remark1_graph_path_and_variable_tau():
+    # unequal mu/rho (tau_g varies in space), a body force, >= 64 steps
+    w = W.random_smooth(4, 100, 90, seed=43, wall_y=True, accept=oracle_accepts)
+    w.gx, w.gy = 2e-6, -3e-6
+    assert max(_parity(w, 150)) < TOL
+
+
+@pytest.mark.parametrize("N", [3, 5])
+def test_remark1_fp32_vs_fp64(N):
+    w = W.random_smooth(N, 160, 96, seed=60 + N, wall_y=True, accept=oracle_accepts)
+    a = gpu_domain(w, precision=64, force_form=1)
+    b = gpu_domain(w, precision=32, force_form=1)
+    a.step(500)
+    b.step(500)
+    ca, _, _ = a.macro()
+    cb, _, _ = b.macro()
+    assert maxabs(ca, cb) < 1e-5
+
+
+def test_remark1_mass_conserved():
+    w = W.random_smooth(5, 128, 96, seed=65, wall_y=True, accept=oracle_accepts)
+    d = gpu_domain(w, precision=64, force_form=1)
+    m0, _, _ = d.diagnostics()
+    d.step(2000)
+    m1, dev, bad = d.diagnostics()
+    d.close()
+    assert bad == 0 and dev < 1e-12
+    assert np.max(np.abs(m1 - m0) / m0) < 1e-12
+
+
+def test_remark1_is_not_the_eq_N20_1_form():
+    # the parity above would also hold if both sides ignored force_form:
+    # the GPU run must sit on the oracle's form 1 and measurably off form 0
+    w = W.random_smooth(3, 64, 48, seed=72, wall_y=True, accept=oracle_accepts)
+    assert np.ptp(w.rho) > 0.5
+    o0 = oracle_run(w, 40, force_form=0).macro()
+    o1 = oracle_run(w, 40, force_form=1).macro()
+    d = gpu_domain(w, force_form=1)
+    d.step(40)
+    r1 = d.macro()
+    d.close()
+    gap = maxabs(r1[1], o1[1])
+    off = maxabs(r1[1], o0[1])
+    print(f"u: |gpu - form 1| = {gap:.3e}, |gpu - form 0| = {off:.3e}")
+    assert gap < TOL
+    assert off > 1e-8 and off > 100 * gap
+
+
+def test_remark1_serving_alone_equals_mix():
+    import paper_1904_12553_amd as P
+    wa = W.random_smooth(3, 96, 64, seed=81, wall_y=True, accept=P.accepts)
+    wb = W.random_smooth(5, 64, 80, seed=82, wall_y=False, accept=P.accepts)
+    wc = W.random_smooth(4, 80, 48, seed=83, wall_y=True, accept=P.accepts)
+    jobs = [(wa, dict(force_form=1), 70), (wb, dict(grad_scheme=1), 45),
+            (wc, dict(force_form=1), 90), (wb, dict(), 30)]
+    srv = P.Server(hbm_budget=1 << 30, max_slots=4, quantum=16)
+    tickets = [srv.submit(w.c, w.u, nsteps=n, precision=32, **dict(w.params(), **kw))
+               for w, kw, n in jobs]
+    results = {}
+    for _ in range(1000):
+        srv.pump()
+        for t in tickets:
+            if t not in results and srv.poll(t) == 2:
+                results[t] = srv.result(t)
+        if len(results) == len(tickets):
+            break
+    assert len(results) == len(tickets)
+    for t, (w, kw, n) in zip(tickets, jobs):
+        d = gpu_domain(w, precision=32, **kw)
+        d.step(n)
+        alone = d.macro()
+        d.close()
+        for x, y in zip(results[t][:3], alone):
+            assert np.array_equal(x, y)
