@@ -7,6 +7,7 @@ GPU library and the GPU library never calls it.
 Two independent CPU implementations live here:
 
 * ``OracleSim`` -- ctypes wrapper over ``nplbm_oracle.c`` (plain C, FP64);
+* ``OracleSim3D`` -- the same model on the D3Q15 lattice, ``nplbm_oracle3d.c``;
 * ``oracle.literal`` -- a NumPy transcription over whole arrays that keeps all
   nine NS populations (including g_0 and rho_0), used to cross-check the C
   oracle on tiny grids.
@@ -27,8 +28,8 @@ def _lib():
     global _LIB
     if _LIB is None:
         path = os.path.join(HERE, "liboracle.so")
-        src = os.path.join(HERE, "nplbm_oracle.c")
-        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src):
+        srcs = [os.path.join(HERE, f) for f in ("nplbm_oracle.c", "nplbm_oracle3d.c")]
+        if not os.path.exists(path) or os.path.getmtime(path) < max(map(os.path.getmtime, srcs)):
             from . import build_oracle as _b
             _b.build()
         lib = ctypes.CDLL(path)
@@ -55,6 +56,21 @@ def _lib():
         lib.orc_node_dists.argtypes = [vp] + [d] * 11 + [P, P]
         lib.orc_node_heq.argtypes = [vp, i, d, d, d, d, P]
         lib.orc_stencils.argtypes = [vp, P, P, P]
+        lib.orc3_create.argtypes = [i, i, i, i, i, P, P, P, P, P, d, d, d, d, d,
+                                    ctypes.POINTER(vp)]
+        lib.orc3_create.restype = i
+        lib.orc3_free.argtypes = [vp]
+        lib.orc3_init.argtypes = [vp, P, P]
+        lib.orc3_step.argtypes = [vp, l]
+        lib.orc3_macro.argtypes = [vp, P, P, P]
+        lib.orc3_fields.argtypes = [vp, P, P, P, P, P, P]
+        lib.orc3_mass.argtypes = [vp, P]
+        lib.orc3_time.argtypes = [vp]
+        lib.orc3_time.restype = l
+        lib.orc3_get_state.argtypes = [vp, P, P, P, P]
+        lib.orc3_node_dists.argtypes = [vp, d, d, P, P, P, P, d, P, P]
+        lib.orc3_node_heq.argtypes = [vp, i, d, d, P, P]
+        lib.orc3_stencils.argtypes = [vp, P, P, P]
         _LIB = lib
     return _LIB
 
@@ -207,6 +223,103 @@ class OracleSim:
         lap = np.empty((self.ny, self.nx))
         g = np.empty((2, self.ny, self.nx))
         _lib().orc_stencils(self._h, _p(f), _p(lap), _p(g))
+        return lap, g
+
+
+class OracleSim3D:
+    """One 3-D domain (D3Q15 lattice of Sec. 3.1) in the FP64 oracle.
+
+    Same parameters as ``OracleSim`` plus ``nz``; x and y are periodic, z is
+    periodic or bounded by halfway bounce-back walls (``wall_z``); the body
+    force is rho (gx, gy, gz).  Fields have shape (.., nz, ny, nx)."""
+
+    def __init__(self, N, nx, ny, nz, sigma, rho, mu, mobility=0.1, tau_phi=0.8, W=4.0,
+                 wall_z=False, gx=0.0, gy=0.0, gz=0.0, rho0=1.0):
+        lib = _lib()
+        self.N, self.nx, self.ny, self.nz = int(N), int(nx), int(ny), int(nz)
+        sig = np.ascontiguousarray(np.asarray(sigma, dtype=np.float64).reshape(N, N))
+        r, m = _arr(rho, N), _arr(mu, N)
+        mob, tp = _arr(mobility, N - 1), _arr(tau_phi, N - 1)
+        h = ctypes.c_void_p()
+        rc = lib.orc3_create(self.N, self.nx, self.ny, self.nz, int(bool(wall_z)), _p(sig),
+                             _p(r), _p(m), _p(mob), _p(tp), float(W), float(gx), float(gy),
+                             float(gz), float(rho0), ctypes.byref(h))
+        if rc != 0:
+            raise OracleError(rc)
+        self._h = h
+        self._keep = (sig, r, m, mob, tp)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib().orc3_free(h)
+            self._h = None
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    def init(self, c, u=None):
+        c = np.ascontiguousarray(c, dtype=np.float64).reshape((self.N,) + self.shape)
+        uu = None if u is None else np.ascontiguousarray(u, dtype=np.float64).reshape(
+            (3,) + self.shape)
+        _lib().orc3_init(self._h, _p(c), _p(uu))
+
+    def step(self, nsteps=1):
+        _lib().orc3_step(self._h, int(nsteps))
+
+    @property
+    def time(self):
+        return _lib().orc3_time(self._h)
+
+    def macro(self):
+        c = np.empty((self.N,) + self.shape)
+        u = np.empty((3,) + self.shape)
+        p = np.empty(self.shape)
+        _lib().orc3_macro(self._h, _p(c), _p(u), _p(p))
+        return c, u, p
+
+    def fields(self):
+        sh = self.shape
+        out = dict(phi=np.empty((self.N - 1,) + sh), rho=np.empty(sh),
+                   C=np.empty((self.N - 1,) + sh), F=np.empty((3,) + sh),
+                   J=np.empty((3,) + sh), grho=np.empty((3,) + sh))
+        _lib().orc3_fields(self._h, _p(out["phi"]), _p(out["rho"]), _p(out["C"]),
+                           _p(out["F"]), _p(out["J"]), _p(out["grho"]))
+        return out
+
+    def mass(self):
+        m = np.empty(self.N)
+        _lib().orc3_mass(self._h, _p(m))
+        return m
+
+    def get_state(self):
+        sh = self.shape
+        h = np.empty((self.N - 1, 15) + sh)
+        g = np.empty((15,) + sh)
+        pp = np.empty((self.N - 1,) + sh)
+        pu = np.empty((3,) + sh)
+        _lib().orc3_get_state(self._h, _p(h), _p(g), _p(pp), _p(pu))
+        return h, g, pp, pu
+
+    def node_dists(self, rho, p, u, F, grho, J, taug):
+        geq, G = np.empty(15), np.empty(15)
+        a = [np.ascontiguousarray(v, dtype=np.float64) for v in (u, F, grho, J)]
+        _lib().orc3_node_dists(self._h, float(rho), float(p), _p(a[0]), _p(a[1]), _p(a[2]),
+                               _p(a[3]), float(taug), _p(geq), _p(G))
+        return geq, G
+
+    def node_heq(self, i, phi, C, u):
+        heq = np.empty(15)
+        uu = np.ascontiguousarray(u, dtype=np.float64)
+        _lib().orc3_node_heq(self._h, int(i), float(phi), float(C), _p(uu), _p(heq))
+        return heq
+
+    def stencils(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(self.shape)
+        lap = np.empty(self.shape)
+        g = np.empty((3,) + self.shape)
+        _lib().orc3_stencils(self._h, _p(f), _p(lap), _p(g))
         return lap, g
 
 

@@ -9,13 +9,15 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "nplbm_oracle.c")
+SRC3 = os.path.join(HERE, "nplbm_oracle3d.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     cmd = ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math",
-           "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wno-unused-function", SRC, "-o", tmp, "-lm"]
+           "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wno-unused-function", SRC, SRC3, "-o", tmp,
+           "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
