@@ -43,7 +43,7 @@ def log(*a):
 
 def kernel_hash():
     h = hashlib.sha256()
-    for f in ("step_kernel.hip", "nplbm_internal.h", "lattice.h"):
+    for f in ("step_kernel.hip", "buffer_io.h", "nplbm_internal.h", "lattice.h"):
         with open(os.path.join(ROOT, "paper_1904_12553_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -87,6 +87,31 @@ def time_steps(d, steps, torch, stream, diag_every=DIAG_EVERY):
     return wall, kern, diag
 
 
+def kernel_rate(P, w, prec, steps, torch, stream, **over):
+    """Step-kernel time of a workload (HIP events around `steps` steps after
+    a warmup): ms per step, MLUPS and the fraction of the HBM roofline with
+    the algorithmic bytes per node update -- 20 N s on D2Q9, 2 (16 N + 1) s
+    on D3Q15 -- for state word size s."""
+    d = P.Domain(precision=prec, **dict(w.params(), **over))
+    d.set_fields(w.c, w.u)
+    d.step(64)
+    d.sync()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    d.step(steps)
+    b.record(stream)
+    b.synchronize()
+    ms = a.elapsed_time(b) / steps
+    nodes = d.n
+    s = 8 if prec == 64 else 4
+    B = (2 * (16 * w.N + 1) if d.dim == 3 else 20 * w.N) * s
+    d.close()
+    return {"kernel_ms": round(ms, 5), "MLUPS": round(nodes / ms / 1e3, 1),
+            "bytes_per_node_update": B,
+            "roofline_frac": round(nodes * B / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +127,8 @@ def main():
     ap.add_argument("--serving-steps-scale", type=float, default=0.1)
     ap.add_argument("--profile-only", action="store_true",
                     help="only the warmup and timed FP32 steps (for rocprofv3 runs)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the N = 3 / 4 sweep, the Remark 1 and the D3Q15 legs")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -199,6 +226,39 @@ def main():
     a32.close()
     a64.close()
     del a32, a64
+
+    if not args.no_extra:
+        # ---- the other phase counts at sizes far above the 256 MB MALL ----
+        sweep = []
+        for name, wk in (("static_droplet_N3_4096x4096", lambda: W.static_droplet(4096, 4096, R=1000)),
+                         ("droplet_collision_N4_3072x3072",
+                          lambda: W.droplet_collision(3072, accept=P.accepts))):
+            ww = wk()
+            for prec in (32, 64):
+                sweep.append(dict(workload=name, precision=f"fp{prec}",
+                                  **kernel_rate(P, ww, prec, 200 if prec == 32 else 100, torch,
+                                                stream)))
+                log(f"[bench] {name} fp{prec}: {sweep[-1]}")
+            del ww
+        out["sweep_2d"] = sweep
+        # ---- force distribution of Remark 1 against eq:N20_1, same workload ----
+        r1 = kernel_rate(P, w, 32, 300, torch, stream, force_form=1)
+        r1["vs_eq_N20_1_kernel_time"] = round(r1["kernel_ms"] / k_ms, 3)
+        out["remark1_force"] = r1
+        log(f"[bench] remark 1: {r1}")
+        # ---- D3Q15 ----
+        d3 = []
+        for name, wk in (("static_sphere_N3_256^3", lambda: W.static_sphere(256, R=64.0)),
+                         ("slabs_spheres_N5_256^3",
+                          lambda: W.slabs_and_spheres(256, accept=P.accepts))):
+            ww = wk()
+            for prec in (32, 64):
+                d3.append(dict(workload=name, precision=f"fp{prec}",
+                               **kernel_rate(P, ww, prec, 100 if prec == 32 else 50, torch,
+                                             stream)))
+                log(f"[bench] {name} fp{prec}: {d3[-1]}")
+            del ww
+        out["d3q15"] = d3
 
     # ---- serving ----
     if not args.no_serving:

@@ -76,6 +76,16 @@ enum {
  *   interface_width W > 0; the interface scale is eta = W / (2 sqrt 2), so
  *                   the equilibrium profile is 1/2 + 1/2 tanh(2 x / W)
  *   gx, gy          body-force acceleration, G = rho (gx, gy) (Sec. 2)
+ *   gz              z component of the body-force acceleration (3-D only)
+ *   nz              0 or 1: a 2-D domain on the D2Q9 lattice; >= 4: a 3-D
+ *                   domain of nx x ny x nz nodes on the D3Q15 lattice of
+ *                   Sec. 3.1 (x and y periodic; N <= 5, grad_scheme 0,
+ *                   force_form 0 and wall_y 0 are required, else
+ *                   NPLBM_EINVAL).  Fields of a 3-D domain are
+ *                   f[((f * nz + z) * ny + y) * nx + x] and u has three
+ *                   components.
+ *   wall_z          3-D only: 0 periodic in z; 1 halfway bounce-back walls
+ *                   below plane 0 and above plane nz-1
  *
  * Derived on the host (Sec. 2 and eq:N36): beta^2 = 3 sqrt(2) sigma_min eta,
  * lambda_ij from eq:N14-N16, eta_i = m_i / (c_s^2 (tau_i - 1/2)) (eq:N30);
@@ -95,6 +105,9 @@ typedef struct nplbm_params {
   const double *tau_phi;
   double interface_width;
   double gx, gy;
+  double gz;
+  int32_t nz;
+  int32_t wall_z;
 } nplbm_params;
 
 typedef struct nplbm_domain nplbm_domain;

@@ -20,7 +20,8 @@ LIB = os.path.join(HERE, "libnplbm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["step_kernel.hip", "step_kernel_mixed.hip", "step_kernel_remark1.hip",
-           "aux_kernels.hip", "nplbm_host.cpp", "nplbm_api.cpp", "nplbm_server.cpp"]
+           "step3d_kernel.hip", "aux_kernels.hip", "aux3d_kernels.hip", "nplbm_host.cpp",
+           "nplbm_api.cpp", "nplbm_server.cpp"]
 
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
           "-Wall", "-Wno-unused-function", "-Wno-unused-variable",

@@ -25,6 +25,9 @@ struct Derived {
   Consts<float> cf;
 };
 int derive(const nplbm_params *p, Derived &d);
+// 3-D (D3Q15) domain: nz >= 4; planes in z (1 for a 2-D domain)
+inline bool is3d(const nplbm_params *p) { return p->nz > 1; }
+inline int dom_nz(const nplbm_params *p) { return p->nz > 1 ? p->nz : 1; }
 
 // Byte offsets of every device buffer of one domain inside its allocation.
 struct Layout {
@@ -55,5 +58,8 @@ int resident_step_blocks(int N, int precision, int scheme);
 void build_strips(int nx, int ny, int dom, const StepGeom &geom, std::vector<StripDesc> &out,
                   int target = 0);
 void xcd_order(std::vector<StripDesc> &s);
+// tiles of the 3-D step kernel, stored as TileDesc3 records
+void build_tiles3(int nx, int ny, int nz, int dom, int ty, int target,
+                  std::vector<StripDesc> &out);
 
 }  // namespace nplbm

@@ -28,6 +28,8 @@ struct nplbm_domain {
   StripDesc *strips_dev = nullptr;
   int nstrips = 0;
   StepGeom geom{64, 60, 1};  // strip geometry of the step kernel
+  bool d3 = false;           // 3-D (D3Q15) domain
+  int ty = 8;                // tile rows of the 3-D step kernel
   int64_t t = 0;
   bool initialised = false;
   // graph of kGraphSteps consecutive steps starting from an even time
@@ -41,14 +43,31 @@ constexpr int kGraphSteps = 64;
 
 double *dptr(nplbm_domain *d, size_t off) { return reinterpret_cast<double *>(d->base + off); }
 
+size_t nnodes(const nplbm_domain *d) { return (size_t)d->p.nx * d->p.ny * dom_nz(&d->p); }
+
+hipError_t launch_any_step(nplbm_domain *d, const StepArgs &a) {
+  if (d->d3) return launch_step3(d->p.N, d->p.precision, d->ty, a, d->nstrips, d->stream);
+  return launch_step(d->p.N, d->p.precision, step_scheme(&d->p), d->geom.bw, a, d->nstrips,
+                     d->stream);
+}
+
+// resident 3-D step workgroups on the device (0 if unknown)
+int resident_step3_blocks(int N, int precision, int ty) {
+  int dev = 0, cus = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    cus = prop.multiProcessorCount;
+  const int per = step3_blocks_per_cu(N, precision, ty);
+  return cus > 0 && per > 0 ? cus * per : 0;
+}
+
 int launch_one_step(nplbm_domain *d) {
   StepArgs a;
   std::memset(&a, 0, sizeof a);
   a.strips = d->strips_dev;
   a.doms = d->desc_dev;
   a.substep = (int)(d->t & 1);
-  hipError_t e = launch_step(d->p.N, d->p.precision, step_scheme(&d->p), d->geom.bw, a,
-                             d->nstrips, d->stream);
+  hipError_t e = launch_any_step(d, a);
   if (e != hipSuccess) return hip_fail(e, "step launch");
   d->t += 1;
   return NPLBM_OK;
@@ -67,8 +86,7 @@ int capture_graph(nplbm_domain *d) {
   hipError_t le = hipSuccess;
   for (int s = 0; s < kGraphSteps && le == hipSuccess; ++s) {
     a.substep = s & 1;
-    le = launch_step(d->p.N, d->p.precision, step_scheme(&d->p), d->geom.bw, a, d->nstrips,
-                     d->stream);
+    le = launch_any_step(d, a);
   }
   e = hipStreamEndCapture(d->stream, &g);
   if (le != hipSuccess) {
@@ -88,6 +106,14 @@ int capture_graph(nplbm_domain *d) {
 
 int readback(nplbm_domain *d, bool want_up) {
   const int par = (int)(d->t & 1);
+  if (d->d3) {
+    hipError_t e = launch_macro3(d->desc_dev, d->desc, d->p.precision, par, dptr(d, d->L.phi),
+                                 dptr(d, d->L.rho), dptr(d, d->L.C), dptr(d, d->L.c),
+                                 want_up ? dptr(d, d->L.u) : nullptr,
+                                 want_up ? dptr(d, d->L.p) : nullptr, d->stream);
+    if (e != hipSuccess) return hip_fail(e, "macro launch");
+    return NPLBM_OK;
+  }
   hipError_t e = launch_macro(d->desc_dev, d->desc, d->p.precision, par, dptr(d, d->L.phi),
                               dptr(d, d->L.rho), dptr(d, d->L.C), dptr(d, d->L.c),
                               want_up ? dptr(d, d->L.u) : nullptr,
@@ -199,8 +225,9 @@ int nplbm_create(const nplbm_params *p, void *stream, void *device_mem, size_t d
   }
   D.nx = p->nx;
   D.ny = p->ny;
+  D.nz = dom_nz(p);
   D.pitch = d->L.pitch;
-  D.wall = p->wall_y;
+  D.wall = is3d(p) ? p->wall_z : p->wall_y;
   D.N = N;
   D.parity0 = 0;
   D.steps_left = INT_MAX;
@@ -209,8 +236,16 @@ int nplbm_create(const nplbm_params *p, void *stream, void *device_mem, size_t d
   D.cf = d->d.cf;
   d->desc_dev = reinterpret_cast<DomDesc *>(d->base + d->L.desc);
   std::vector<StripDesc> strips;
-  d->geom = step_geom(p->N, p->precision, step_scheme(p));
-  build_strips(p->nx, p->ny, 0, d->geom, strips, single_domain_target(p));
+  d->d3 = is3d(p);
+  if (d->d3) {
+    d->ty = step3_ty(N, p->precision);
+    int target = resident_step3_blocks(N, p->precision, d->ty);
+    if (const char *env = std::getenv("NPLBM_TARGET_BLOCKS")) target = std::atoi(env);
+    build_tiles3(p->nx, p->ny, p->nz, 0, d->ty, target, strips);
+  } else {
+    d->geom = step_geom(p->N, p->precision, step_scheme(p));
+    build_strips(p->nx, p->ny, 0, d->geom, strips, single_domain_target(p));
+  }
   xcd_order(strips);
   if ((int)strips.size() > d->L.nstrips) {
     nplbm_destroy(d);
@@ -236,7 +271,8 @@ int nplbm_set_fields(nplbm_domain *d, const double *c, const double *u) {
   clear_error();
   if (!check_domain(d) || !c) return fail(NPLBM_EINVAL, "NULL domain or c");
   const int N = d->p.N;
-  const size_t n = (size_t)d->p.nx * d->p.ny;
+  const size_t n = nnodes(d);
+  const int nu = d->d3 ? 3 : 2;
   for (size_t id = 0; id < n; ++id) {
     double s = 0.0;
     for (int k = 0; k < N; ++k) {
@@ -248,16 +284,17 @@ int nplbm_set_fields(nplbm_domain *d, const double *c, const double *u) {
       return fail(NPLBM_EINVAL, "sum_k c_k = %.17g at node %zu (must be 1)", s, id);
   }
   if (u)
-    for (size_t id = 0; id < 2 * n; ++id)
+    for (size_t id = 0; id < nu * n; ++id)
       if (!std::isfinite(u[id])) return fail(NPLBM_EINVAL, "u is not finite");
   hipError_t e = hipMemcpyAsync(dptr(d, d->L.c), c, (size_t)N * n * 8, hipMemcpyHostToDevice,
                                 d->stream);
   if (e == hipSuccess && u)
-    e = hipMemcpyAsync(dptr(d, d->L.u), u, 2 * n * 8, hipMemcpyHostToDevice, d->stream);
+    e = hipMemcpyAsync(dptr(d, d->L.u), u, nu * n * 8, hipMemcpyHostToDevice, d->stream);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync H2D");
-  e = launch_init(d->desc_dev, d->desc, d->p.precision, d->d.P1, d->d.PN, d->d.P0,
-                  dptr(d, d->L.c), u ? dptr(d, d->L.u) : nullptr, dptr(d, d->L.phi),
-                  dptr(d, d->L.C), d->stream);
+  e = (d->d3 ? launch_init3 : launch_init)(d->desc_dev, d->desc, d->p.precision, d->d.P1,
+                                           d->d.PN, d->d.P0, dptr(d, d->L.c),
+                                           u ? dptr(d, d->L.u) : nullptr, dptr(d, d->L.phi),
+                                           dptr(d, d->L.C), d->stream);
   if (e != hipSuccess) return hip_fail(e, "init launch");
   e = hipStreamSynchronize(d->stream);
   if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
@@ -297,7 +334,7 @@ int nplbm_get_c(nplbm_domain *d, double *c) {
   if (!d->initialised) return fail(NPLBM_ESTATE, "nplbm_set_fields was not called");
   int rc = readback(d, false);
   if (rc) return rc;
-  return copy_out(d, c, d->L.c, (size_t)d->p.N * d->p.nx * d->p.ny * 8);
+  return copy_out(d, c, d->L.c, (size_t)d->p.N * nnodes(d) * 8);
 }
 
 int nplbm_get_u(nplbm_domain *d, double *u) {
@@ -306,7 +343,7 @@ int nplbm_get_u(nplbm_domain *d, double *u) {
   if (!d->initialised) return fail(NPLBM_ESTATE, "nplbm_set_fields was not called");
   int rc = readback(d, true);
   if (rc) return rc;
-  return copy_out(d, u, d->L.u, (size_t)2 * d->p.nx * d->p.ny * 8);
+  return copy_out(d, u, d->L.u, (size_t)(d->d3 ? 3 : 2) * nnodes(d) * 8);
 }
 
 int nplbm_get_p(nplbm_domain *d, double *p) {
@@ -315,7 +352,7 @@ int nplbm_get_p(nplbm_domain *d, double *p) {
   if (!d->initialised) return fail(NPLBM_ESTATE, "nplbm_set_fields was not called");
   int rc = readback(d, true);
   if (rc) return rc;
-  return copy_out(d, p, d->L.p, (size_t)d->p.nx * d->p.ny * 8);
+  return copy_out(d, p, d->L.p, nnodes(d) * 8);
 }
 
 int nplbm_diagnostics(nplbm_domain *d, double *mass_out, double *max_sum_dev,
@@ -326,7 +363,7 @@ int nplbm_diagnostics(nplbm_domain *d, double *mass_out, double *max_sum_dev,
   int rc = readback(d, false);
   if (rc) return rc;
   const int N = d->p.N;
-  const int64_t n = (int64_t)d->p.nx * d->p.ny;
+  const int64_t n = (int64_t)nnodes(d);
   hipError_t e = launch_diag(dptr(d, d->L.c), N, n, dptr(d, d->L.partials), d->L.nblk,
                              dptr(d, d->L.out), d->stream);
   if (e != hipSuccess) return hip_fail(e, "diag launch");
@@ -345,6 +382,7 @@ int nplbm_laplace(nplbm_domain *d, double xc, double yc, double r_in, double r_o
   if (!check_domain(d) || !dp) return fail(NPLBM_EINVAL, "NULL argument");
   if (!d->initialised) return fail(NPLBM_ESTATE, "nplbm_set_fields was not called");
   if (!(r_in >= 0.0) || !(r_out >= r_in)) return fail(NPLBM_EINVAL, "need 0 <= r_in <= r_out");
+  if (d->d3) return fail(NPLBM_EINVAL, "nplbm_laplace measures 2-D domains only");
   int rc = readback(d, true);
   if (rc) return rc;
   hipError_t e = launch_laplace(dptr(d, d->L.p), d->p.nx, d->p.ny, xc, yc, r_in, r_out,

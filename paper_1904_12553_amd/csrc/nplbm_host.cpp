@@ -95,13 +95,25 @@ int derive(const nplbm_params *p, Derived &d) {
   if (N < 2 || N > NPLBM_MAX_PHASES)
     return fail(NPLBM_EINVAL, "N=%d outside [2, %d]", N, NPLBM_MAX_PHASES);
   if (p->nx < 4 || p->ny < 4) return fail(NPLBM_EINVAL, "nx, ny must be >= 4");
-  if ((int64_t)p->nx * p->ny > (int64_t)1 << 30)
+  if (p->nz < 0 || p->nz == 2 || p->nz == 3) return fail(NPLBM_EINVAL, "nz must be 0, 1 or >= 4");
+  if ((int64_t)p->nx * p->ny * dom_nz(p) > (int64_t)1 << 30)
     return fail(NPLBM_EINVAL, "domain larger than 2^30 nodes");
+  if (is3d(p)) {
+    if (N > 5) return fail(NPLBM_EINVAL, "3-D domains are built for N <= 5");
+    if (p->grad_scheme != kGradCentral || p->force_form != 0)
+      return fail(NPLBM_EINVAL, "3-D domains use grad_scheme 0 and force_form 0");
+    if (p->wall_y != 0) return fail(NPLBM_EINVAL, "3-D domains are periodic in y (wall_y 0)");
+    if (p->wall_z != 0 && p->wall_z != 1) return fail(NPLBM_EINVAL, "wall_z must be 0 or 1");
+    if (!std::isfinite(p->gz)) return fail(NPLBM_EINVAL, "gz must be finite");
+  } else if (p->wall_z != 0 || p->gz != 0.0) {
+    return fail(NPLBM_EINVAL, "wall_z and gz apply to 3-D domains (nz >= 4) only");
+  }
   if (p->precision != 32 && p->precision != 64)
     return fail(NPLBM_EINVAL, "precision must be 32 or 64");
   // the step kernel addresses one row block of a state group (all its
   // planes of one lattice row) with 32-bit byte offsets below 2^31
-  if ((int64_t)9 * (N - 1) * (((int64_t)p->nx + 31) & ~(int64_t)31) * (p->precision / 8) >=
+  if ((int64_t)(is3d(p) ? 15 : 9) * (N - 1) * (((int64_t)p->nx + 31) & ~(int64_t)31) *
+          (p->precision / 8) >=
       (int64_t)1 << 31)
     return fail(NPLBM_EINVAL, "nx=%d too large: a row block would exceed 2^31 bytes", p->nx);
   if (p->grad_scheme != kGradCentral && p->grad_scheme != kGradMixed)
@@ -262,6 +274,7 @@ int derive(const nplbm_params *p, Derived &d) {
   }
   K.gx = p->gx;
   K.gy = p->gy;
+  K.gz = is3d(p) ? p->gz : 0.0;
   // constant tau_g when mu~_k / rho~_k is the same for every phase
   const double nu0 = p->mu[0] / p->rho[0];
   bool cst = true;
@@ -295,6 +308,7 @@ int derive(const nplbm_params *p, Derived &d) {
   }
   F.gx = (float)K.gx;
   F.gy = (float)K.gy;
+  F.gz = (float)K.gz;
   F.itau_g = (float)K.itau_g;
   F.src_g = (float)K.src_g;
   F.theta_g = (float)K.theta_g;
@@ -363,19 +377,22 @@ Layout plan_layout(const nplbm_params *p) {
   const size_t s = p->precision == 64 ? 8 : 4;
   L.pitch = (p->nx + 31) & ~31;  // rows start on 128-byte lines
   if (const char *e = std::getenv("NPLBM_PITCH_PAD")) L.pitch += std::max(0, std::atoi(e)) & ~31;
-  const size_t n = (size_t)p->nx * p->ny;
-  const int np[3] = {M * 9, 8, M + 2};  // planes per group
+  const bool d3 = is3d(p);
+  const int nrows = p->ny * dom_nz(p);  // (z, y) lines of nodes
+  const size_t n = (size_t)p->nx * nrows;
+  // planes per group: CH populations, NS populations k >= 1, previous phi and u
+  const int np[3] = {M * (d3 ? 15 : 9), d3 ? 14 : 8, M + (d3 ? 3 : 2)};
   const char *lay = std::getenv("NPLBM_LAYOUT");
   const bool soa = lay && std::strcmp(lay, "soa") == 0;
   for (int G = 0; G < 3; ++G) {
     if (soa) {
-      L.ps[G] = (int64_t)L.pitch * p->ny + plane_pad(s);
+      L.ps[G] = (int64_t)L.pitch * nrows + plane_pad(s);
       L.rs[G] = L.pitch;
       L.gbytes[G] = (size_t)np[G] * L.ps[G] * s;
     } else {
       L.ps[G] = L.pitch;
       L.rs[G] = (int64_t)np[G] * L.pitch + row_pad(s);
-      L.gbytes[G] = (size_t)p->ny * L.rs[G] * s;
+      L.gbytes[G] = (size_t)nrows * L.rs[G] * s;
     }
   }
   size_t off = 0;
@@ -389,14 +406,16 @@ Layout plan_layout(const nplbm_params *p) {
   for (int b = 0; b < 2; ++b) L.prev[b] = take(L.gbytes[2]);
   L.state_end = off;
   L.desc = take(sizeof(DomDesc));
-  // room for any strip decomposition (strip height >= 2, XCD padding)
-  L.nstrips = ((p->nx + 7) / 8) * ((p->ny + 1) / 2) + 8;
+  // room for any strip decomposition (strip height >= 2, XCD padding), or
+  // for the 3-D tiles (at least 4 x 4 nodes and 2 planes each)
+  L.nstrips = d3 ? ((p->nx + 3) / 4) * ((p->ny + 3) / 4) * ((dom_nz(p) + 1) / 2) + 8
+                 : ((p->nx + 7) / 8) * ((p->ny + 1) / 2) + 8;
   L.strips = take(sizeof(StripDesc) * (size_t)L.nstrips);
   L.phi = take((size_t)M * n * 8);
   L.rho = take(n * 8);
   L.C = take((size_t)M * n * 8);
   L.c = take((size_t)N * n * 8);
-  L.u = take(2 * n * 8);
+  L.u = take((d3 ? 3 : 2) * n * 8);
   L.p = take(n * 8);
   // the products J~_b u_a of the Remark 1 force, for the read-back
   L.q = p->force_form == 1 ? take(4 * n * 8) : 0;
@@ -493,6 +512,46 @@ void xcd_order(std::vector<StripDesc> &s) {
     out[(size_t)j * 8 + g] = s[i];
   }
   s.swap(out);
+}
+
+// Tile decomposition of a 3-D domain for the marching 3-D step kernel:
+// tiles of at most 60 x (ty - 4) interior nodes in (x, y), as equal as
+// possible, each marching through nz / nsz planes, nsz chosen so that the
+// launch has about `target` workgroups; neighbouring z segments march in
+// opposite directions.
+void build_tiles3(int nx, int ny, int nz, int dom, int ty, int target,
+                  std::vector<StripDesc> &out) {
+  auto split = [](int n, int maxw, std::vector<int> &edges) {
+    const int parts = (n + maxw - 1) / maxw;
+    edges.assign(parts + 1, 0);
+    for (int i = 0; i < parts; ++i) edges[i + 1] = edges[i] + n / parts + (i < n % parts ? 1 : 0);
+  };
+  std::vector<int> xs, ys;
+  split(nx, 60, xs);
+  split(ny, ty - 4, ys);
+  const int nxy = (int)((xs.size() - 1) * (ys.size() - 1));
+  if (target <= 0) target = 1024;
+  int nsz = std::max(1, target / std::max(1, nxy));
+  int H = (nz + nsz - 1) / nsz;
+  H = std::max(H, std::min(nz, 8));
+  nsz = (nz + H - 1) / H;
+  for (int sz = 0; sz < nsz; ++sz)
+    for (size_t iy = 0; iy + 1 < ys.size(); ++iy)
+      for (size_t ix = 0; ix + 1 < xs.size(); ++ix) {
+        TileDesc3 t;
+        t.dom = dom;
+        t.x0 = xs[ix];
+        t.x1 = xs[ix + 1];
+        t.y0 = ys[iy];
+        t.y1 = ys[iy + 1];
+        t.z0 = sz * H;
+        t.z1 = std::min(nz, (sz + 1) * H);
+        t.dir = (sz & 1) ? -1 : 1;
+        StripDesc s;
+        static_assert(sizeof s == sizeof t, "record sizes");
+        std::memcpy(&s, &t, sizeof s);
+        out.push_back(s);
+      }
 }
 
 }  // namespace nplbm

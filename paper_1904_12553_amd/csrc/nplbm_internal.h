@@ -58,7 +58,7 @@ struct Consts {
   Real eta_i[kMaxM];     // eq:N30
   Real itau_i[kMaxM];    // 1 / tau_i
   Real src_i[kMaxM];     // 1 - 1 / (2 tau_i), eq:N26
-  Real gx, gy;
+  Real gx, gy, gz;
   Real itau_g, src_g, theta_g;  // used when tau_g is constant
   int32_t const_tau;
   int32_t pad_;
@@ -80,6 +80,12 @@ struct DomDesc {
   int32_t parity0;   // buffer holding the current state at substep 0
   int32_t steps_left;  // substeps >= steps_left do nothing
   int32_t scheme;      // step-kernel scheme (kSchemeCentral / Mixed / Remark1)
+  // Three-dimensional (D3Q15) domains: nz > 1.  Rows are then the (z, y)
+  // lines of nodes, row index z * ny + y; groups hold 15 (N-1) CH planes,
+  // 14 NS planes (k = 1..14) and (N-1) + 3 previous-step planes; `wall`
+  // means halfway bounce-back walls below plane 0 and above plane nz - 1.
+  int32_t nz;
+  int32_t pad3_;
   Consts<double> cd;
   Consts<float> cf;
 };
@@ -94,6 +100,17 @@ struct StripDesc {
   int32_t x1;  // end of the interior columns (exclusive, <= nx)
   int32_t pad_[2];
 };
+
+// One tile of the 3-D marching step kernel: interior columns [x0, x1),
+// interior rows [y0, y1), interior planes [z0, z1) marched upward (dir = +1)
+// or downward (dir = -1).  dom < 0 marks an empty slot.  Same size as
+// StripDesc, so both live in the same table storage.
+struct TileDesc3 {
+  int32_t dom;
+  int32_t x0, x1, y0, y1, z0, z1;
+  int32_t dir;
+};
+static_assert(sizeof(TileDesc3) == sizeof(StripDesc), "tile and strip records differ");
 
 struct StepArgs {
   const StripDesc *strips;
@@ -117,6 +134,22 @@ hipError_t launch_step_remark1(int N, int precision, int bw, const StepArgs &a, 
 int step_blocks_per_cu_central(int N, int precision, int bw);
 int step_blocks_per_cu_mixed(int N, int precision, int bw);
 int step_blocks_per_cu_remark1(int N, int precision, int bw);
+
+// The 3-D (D3Q15) step kernel: tiles of (64 - 4) x (ty - 4) interior nodes,
+// ty rows of one 64-lane wave each (ty = 8 or 16).
+int step3_ty(int N, int precision);
+hipError_t launch_step3(int N, int precision, int ty, const StepArgs &a, int nblocks,
+                        hipStream_t st);
+int step3_blocks_per_cu(int N, int precision, int ty);
+// 3-D initialisation and read-back, the counterparts of launch_init /
+// launch_macro below on dense (nz * ny * nx) planes; u has 3 planes.
+hipError_t launch_init3(const DomDesc *dd_dev, const DomDesc &dd, int precision,
+                        const double *P1, const double *PN, const double *P0,
+                        const double *c_dev, const double *u_dev, double *phi_tmp,
+                        double *C_tmp, hipStream_t st);
+hipError_t launch_macro3(const DomDesc *dd_dev, const DomDesc &dd, int precision, int parity,
+                         double *phi, double *rho, double *C, double *c_out, double *u_out,
+                         double *p_out, hipStream_t st);
 
 // Initialisation: phi (double, (N-1) planes of nx*ny) is computed from c,
 // then C from phi, then h^eq / g^eq written in pull layout.

@@ -124,6 +124,7 @@ int admit(nplbm_server *s, Req *r) {
   }
   D.nx = r->p.nx;
   D.ny = r->p.ny;
+  D.nz = 1;
   D.pitch = r->L.pitch;
   D.wall = r->p.wall_y;
   D.N = r->p.N;
@@ -293,6 +294,7 @@ int nplbm_submit(nplbm_server *s, const nplbm_params *p, const double *c, const 
   clear_error();
   if (!s || !p || !c || !ticket) return fail(NPLBM_EINVAL, "NULL argument");
   if (nsteps < 0) return fail(NPLBM_EINVAL, "nsteps < 0");
+  if (is3d(p)) return fail(NPLBM_EINVAL, "the server takes 2-D domains (nz 0 or 1)");
   Req *r = new Req();
   int rc = derive(p, r->d);
   if (rc) {

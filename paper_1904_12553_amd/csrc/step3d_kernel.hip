@@ -1,0 +1,516 @@
+// step3d_kernel.hip -- one fused time step of the N-phase phase-field LB
+// model (arXiv:1904.12553) on the D3Q15 lattice of Sec. 3.1, for gfx950.
+//
+// The arithmetic per node is that of the 2-D kernel (step_kernel.hip) with
+// three velocity components: pull streaming, phi_i by eq:N28 (the stored
+// k = 0 value is the deviation h_0 - phi_prev, phi carried as the unevaluated
+// sum phi_prev + (d + sum h_k)), closure eq:N18, C_i with the eq:N31b
+// Laplacian, F and J~ from the eq:N31a gradients, u by eq:N22_1, p by
+// eq:N23, NS collision eq:24 / eq:25 / eq:N20_1, CH collisions
+// eq:N24-N27.  Only eq:N31a's central stencils and eq:N20_1 are built in 3-D.
+//
+// Work decomposition.  A workgroup owns a tile of interior nodes
+// [x0, x1) x [y0, y1) (at most 60 x (ty - 4)) and marches through the planes
+// [z0, z1).  Its threads cover the tile plus a 2-node halo in x and y: one
+// 64-lane wave per row of the extended tile, ty rows.  Each iteration pulls
+// plane mA (all threads; streaming fused into the load, bounce-back at z
+// walls as a uniform choice), sums phi into a 5-plane LDS ring; computes C
+// of plane mA - 1 on the tile plus a ring of one into a 4-plane LDS ring; and
+// collides plane mA - 2 on the interior.  The populations of the collision
+// plane were already read two iterations earlier for phi; they are read
+// again (from L2 / MALL), issued at the start of the iteration so the loads
+// are in flight during the phi and C stages.  D3Q15 stencils reach the six
+// faces and eight corners of a node, so the halo is two nodes for phi and one
+// for C, as in 2-D.
+//
+// Stencils on D3Q15 (eq:N31 with the weights 1/9 and 1/72, c_s^2 = 1/3):
+//   lap   = (8 sum_faces + sum_corners - 56 zeta) / 12
+//   d/dx  = (8 (E - W) + sum_corners c_x zeta) / 24     (likewise y, z)
+#include <cstdlib>
+#include <type_traits>
+
+#include "buffer_io.h"
+#include "lattice3.h"
+#include "nplbm_internal.h"
+
+namespace nplbm {
+
+#define NPL_CONST __attribute__((address_space(4)))
+
+namespace {
+
+constexpr int k3W = 64;   // threads per tile row (one wave)
+constexpr int k3PR = 5;   // phi ring planes
+constexpr int k3CR = 4;   // C ring planes
+
+template <typename Real>
+__device__ __forceinline__ const NPL_CONST Consts<Real> *consts3(const NPL_CONST DomDesc *d);
+template <>
+__device__ __forceinline__ const NPL_CONST Consts<double> *consts3<double>(
+    const NPL_CONST DomDesc *d) {
+  return &d->cd;
+}
+template <>
+__device__ __forceinline__ const NPL_CONST Consts<float> *consts3<float>(
+    const NPL_CONST DomDesc *d) {
+  return &d->cf;
+}
+
+// what the collision of one node reads: CH populations pulled (k = 0: the
+// stored deviation), stored previous phi, NS populations k = 1..14 pulled,
+// stored previous u
+template <int M, typename Real>
+struct Col3 {
+  Real h[M][15];
+  Real hi[M];
+  Real g[15];
+  Real pu[3];
+};
+
+__device__ __forceinline__ int wrap_i(int a, int n) {
+  a %= n;
+  return a < 0 ? a + n : a;
+}
+
+template <int N, typename Real, int TY>
+__global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
+  constexpr int M = N - 1;
+  const NPL_CONST TileDesc3 *tp = (const NPL_CONST TileDesc3 *)a.strips + blockIdx.x;
+  const int dom = tp->dom;
+  if (dom < 0) return;
+  const int x0 = tp->x0, x1 = tp->x1, y0 = tp->y0, y1 = tp->y1, z0 = tp->z0, z1 = tp->z1;
+  const int dir = tp->dir;
+  const NPL_CONST DomDesc *D = (const NPL_CONST DomDesc *)a.doms + dom;
+  if (a.substep >= D->steps_left) return;
+  const int par = (a.substep + D->parity0) & 1;
+  const void *hs = D->h[par], *hd = D->h[par ^ 1];
+  const void *gs = D->g[par], *gd = D->g[par ^ 1];
+  const void *pvs = D->prev[par], *pvd = D->prev[par ^ 1];
+  const NPL_CONST Consts<Real> &K = *consts3<Real>(D);
+  const int nx = D->nx, ny = D->ny, nz = D->nz;
+  const bool wall = D->wall != 0;
+  constexpr uint32_t SZ = sizeof(Real);
+  const uint32_t pb = (uint32_t)D->ps[0] * SZ;
+  const uint32_t rbh = (uint32_t)D->rs[0] * SZ, rbg = (uint32_t)D->rs[1] * SZ,
+                 rbp = (uint32_t)D->rs[2] * SZ;
+
+  __shared__ Real sphi[k3PR][M][TY][k3W];
+  __shared__ Real sC[k3CR][M][TY][k3W];
+
+  const int lane = threadIdx.x & (k3W - 1);
+  const int ty = __builtin_amdgcn_readfirstlane(threadIdx.x / k3W);  // uniform
+  const int nxi = x1 - x0, nyi = y1 - y0;
+  const int xc = wrap_i(x0 - 2 + lane, nx);
+  const uint32_t xcu = (uint32_t)xc * SZ;
+  const uint32_t xw = (uint32_t)(xc == 0 ? nx - 1 : xc - 1) * SZ;  // x - 1
+  const uint32_t xe = (uint32_t)(xc == nx - 1 ? 0 : xc + 1) * SZ;  // x + 1
+  const int yc = wrap_i(y0 - 2 + ty, ny);                            // uniform
+  const int yS = yc == 0 ? ny - 1 : yc - 1, yN = yc == ny - 1 ? 0 : yc + 1;
+  const bool lane_int = lane >= 2 && lane < 2 + nxi;
+  const bool row_int = ty >= 2 && ty < 2 + nyi;                      // uniform
+  const bool lane_r1 = lane >= 1 && lane < 3 + nxi;
+  const bool row_r1 = ty >= 1 && ty < 3 + nyi;                       // uniform
+  const int H = z1 - z0;
+
+  auto plane_of = [&](int m) { return dir > 0 ? z0 + m : z1 - 1 - m; };
+  // physical plane of a (possibly ghost) plane index: mirror beyond a wall,
+  // periodic otherwise
+  auto phys_plane = [&](int z) {
+    if (wall) {
+      if (z < 0) z = -1 - z;
+      if (z >= nz) z = 2 * nz - 1 - z;
+      z = z < 0 ? 0 : (z >= nz ? nz - 1 : z);
+    } else {
+      z = wrap_i(z, nz);
+    }
+    return z;
+  };
+  auto ring5 = [](int m) { return (m + 16 * k3PR) % k3PR; };
+  auto ring4 = [](int m) { return (m + 16 * k3CR) % k3CR; };
+
+  // Source of population k arriving at (xc, yc, zp): the node x - c_k, or
+  // the node itself with the opposite direction when z - c_z lies beyond a
+  // wall.  Planes and rows are uniform; the column offset is per lane.
+  struct Src {
+    int zp, zS, zN;  // planes zp, zp - 1, zp + 1 (wrapped)
+    bool bS, bN;     // bounce for c_z = +1 / c_z = -1
+  };
+  auto make_src = [&](int zp) {
+    Src s;
+    s.zp = zp;
+    s.bS = wall && zp == 0;
+    s.bN = wall && zp == nz - 1;
+    s.zS = zp == 0 ? nz - 1 : zp - 1;
+    s.zN = zp == nz - 1 ? 0 : zp + 1;
+    return s;
+  };
+  // buffer resource of the row block (plane, row) a population comes from
+  auto src_rsrc = [&](const void *base, uint32_t rb, const Src &s, int k, int &kk,
+                      uint32_t &co) {
+    const int cx = ex3(k), cy = ey3(k), cz = ez3(k);
+    const bool b = (cz == 1 && s.bS) || (cz == -1 && s.bN);
+    kk = b ? opp3(k) : k;
+    co = b ? xcu : (cx == 1 ? xw : (cx == -1 ? xe : xcu));
+    const int zz = b ? s.zp : (cz == 1 ? s.zS : (cz == -1 ? s.zN : s.zp));
+    const int yy = b ? yc : (cy == 1 ? yS : (cy == -1 ? yN : yc));
+    return row_rsrc(base, rb, zz * ny + yy);
+  };
+
+  // ---- pull what the collision of march index m reads ----
+  // CH populations of phase i
+  auto pull_phase = [&](int m, int i, Col3<M, Real> &P) {
+    const int zp = phys_plane(plane_of(m));
+    const Src s = make_src(zp);
+#pragma unroll
+    for (int k = 0; k < 15; ++k) {
+      int kk;
+      uint32_t co;
+      const Rsrc r = src_rsrc(hs, rbh, s, k, kk, co);
+      P.h[i][k] = bld<Real>(r, co, (uint32_t)(i * 15 + kk) * pb);
+    }
+  };
+  // NS populations, stored previous phi and u
+  auto pull_ns = [&](int m, Col3<M, Real> &P) {
+    const int zp = phys_plane(plane_of(m));
+    const Src s = make_src(zp);
+#pragma unroll
+    for (int k = 1; k < 15; ++k) {
+      int kk;
+      uint32_t co;
+      const Rsrc r = src_rsrc(gs, rbg, s, k, kk, co);
+      P.g[k] = bld<Real>(r, co, (uint32_t)(kk - 1) * pb);
+    }
+    const Rsrc rp = row_rsrc(pvs, rbp, zp * ny + yc);
+#pragma unroll
+    for (int i = 0; i < M; ++i) P.hi[i] = bld<Real>(rp, xcu, (uint32_t)i * pb);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) P.pu[d] = bld<Real>(rp, xcu, (uint32_t)(M + d) * pb);
+  };
+  auto pull_col = [&](int m, Col3<M, Real> &P) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) pull_phase(m, i, P);
+    pull_ns(m, P);
+  };
+
+  // ---- stage A: phi of march index mA -> LDS (all threads) ----
+  auto stageA = [&](int mA) {
+    const int zp = phys_plane(plane_of(mA));
+    const Src s = make_src(zp);
+    Real lo[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) lo[i] = Real(0);
+#pragma unroll
+    for (int k = 0; k < 15; ++k) {
+      int kk;
+      uint32_t co;
+      const Rsrc r = src_rsrc(hs, rbh, s, k, kk, co);
+#pragma unroll
+      for (int i = 0; i < M; ++i) lo[i] += bld<Real>(r, co, (uint32_t)(i * 15 + kk) * pb);
+    }
+    const Rsrc rp = row_rsrc(pvs, rbp, zp * ny + yc);
+    const int slot = ring5(mA);
+#pragma unroll
+    for (int i = 0; i < M; ++i)
+      sphi[slot][i][ty][lane] = bld<Real>(rp, xcu, (uint32_t)i * pb) + lo[i];  // eq:N28
+  };
+
+  // ---- stage B: chemical potentials of march index mB -> LDS ----
+  // On the tile plus a ring of one.  Planes beyond a wall are skipped: the
+  // collision next to the wall reads its own plane for the mirror ghost.
+  auto stageB = [&](int mB) {
+    if (!row_r1 || !lane_r1) return;
+    if (wall) {
+      const int z = plane_of(mB);
+      if (z < 0 || z >= nz) return;
+    }
+    const int s0 = ring5(mB), sU = ring5(mB + dir), sD = ring5(mB - dir);
+    Real phi[M], lap[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      const Real c = sphi[s0][i][ty][lane];
+      const Real faces = (sphi[s0][i][ty][lane + 1] + sphi[s0][i][ty][lane - 1]) +
+                         (sphi[s0][i][ty + 1][lane] + sphi[s0][i][ty - 1][lane]) +
+                         (sphi[sU][i][ty][lane] + sphi[sD][i][ty][lane]);
+      const Real corners =
+          ((sphi[sU][i][ty + 1][lane + 1] + sphi[sU][i][ty + 1][lane - 1]) +
+           (sphi[sU][i][ty - 1][lane + 1] + sphi[sU][i][ty - 1][lane - 1])) +
+          ((sphi[sD][i][ty + 1][lane + 1] + sphi[sD][i][ty + 1][lane - 1]) +
+           (sphi[sD][i][ty - 1][lane + 1] + sphi[sD][i][ty - 1][lane - 1]));
+      lap[i] = (Real(8) * faces + corners - Real(56) * c) * (Real(1) / Real(12));  // eq:N31b
+      phi[i] = c;
+    }
+    Real wv[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      Real ck = K.ca[k];
+#pragma unroll
+      for (int i = 0; i < M; ++i) ck += K.cA[k][i] * phi[i];
+      wv[k] = ck * (Real(1) - ck) * (Real(1) - Real(2) * ck);
+    }
+    const int sc = ring4(mB);
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      Real Ci = Real(0);
+#pragma unroll
+      for (int j = 0; j < M; ++j) Ci -= K.lam[i][j] * lap[j];
+#pragma unroll
+      for (int k = 0; k < N; ++k) Ci += K.KH[k][i] * wv[k];
+      sC[sc][i][ty][lane] = Ci;
+    }
+  };
+
+  // eq:N31a on D3Q15 from an LDS ring: planes s0 (own), sU (z + 1), sD (z - 1)
+  // around column `lane` (clamped by the caller to [1, 62])
+  auto grad3 = [&](const Real (*f)[M][TY][k3W], int lane, int s0, int sU, int sD, int i,
+                   Real &gx, Real &gy, Real &gz) {
+    const Real upp = f[sU][i][ty + 1][lane + 1], upm = f[sU][i][ty + 1][lane - 1];
+    const Real ump = f[sU][i][ty - 1][lane + 1], umm = f[sU][i][ty - 1][lane - 1];
+    const Real dpp = f[sD][i][ty + 1][lane + 1], dpm = f[sD][i][ty + 1][lane - 1];
+    const Real dmp = f[sD][i][ty - 1][lane + 1], dmm = f[sD][i][ty - 1][lane - 1];
+    const Real cx = ((upp - upm) + (ump - umm)) + ((dpp - dpm) + (dmp - dmm));
+    const Real cy = ((upp + upm) - (ump + umm)) + ((dpp + dpm) - (dmp + dmm));
+    const Real cz = ((upp + upm) + (ump + umm)) - ((dpp + dpm) + (dmp + dmm));
+    gx = (Real(8) * (f[s0][i][ty][lane + 1] - f[s0][i][ty][lane - 1]) + cx) * (Real(1) / Real(24));
+    gy = (Real(8) * (f[s0][i][ty + 1][lane] - f[s0][i][ty - 1][lane]) + cy) * (Real(1) / Real(24));
+    gz = (Real(8) * (f[sU][i][ty][lane] - f[sD][i][ty][lane]) + cz) * (Real(1) / Real(24));
+  };
+
+  // ---- stage C: collide march index mC (interior rows) ----
+  // With kLate the NS pulls are issued here and the CH populations of each
+  // phase right before its collision, behind a compiler barrier, so only one
+  // phase's populations are live at a time.
+  auto stageC = [&](int mC, Col3<M, Real> &P, auto kLate) {
+    if constexpr (decltype(kLate)::value) pull_ns(mC, P);
+    const int zp = plane_of(mC);
+    // ghost planes beyond a wall mirror the boundary plane, which is the
+    // collision plane itself; march index mC + dir is plane zp + 1
+    const bool gU = wall && zp + 1 >= nz, gD = wall && zp - 1 < 0;
+    const int s0 = ring5(mC), c0 = ring4(mC);
+    const int sU = gU ? s0 : ring5(mC + dir), sD = gD ? s0 : ring5(mC - dir);
+    const int cU = gU ? c0 : ring4(mC + dir), cD = gD ? c0 : ring4(mC - dir);
+    // x-halo lanes compute on clamped columns and do not store
+    const int ln = lane < 1 ? 1 : (lane > k3W - 2 ? k3W - 2 : lane);
+    Real phi[M], Cv[M];
+    Real rho = K.ra, gr[3] = {Real(0), Real(0), Real(0)}, F[3] = {Real(0), Real(0), Real(0)},
+         J[3] = {Real(0), Real(0), Real(0)};
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      phi[i] = sphi[s0][i][ty][ln];
+      Cv[i] = sC[c0][i][ty][ln];
+      Real gp[3], gc[3];
+      grad3(sphi, ln, s0, sU, sD, i, gp[0], gp[1], gp[2]);
+      grad3(sC, ln, c0, cU, cD, i, gc[0], gc[1], gc[2]);
+      rho += K.rA[i] * phi[i];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        gr[d] += K.rA[i] * gp[d];
+        F[d] += Cv[i] * gp[d];
+        J[d] += K.Jc[i] * gc[d];
+      }
+    }
+    F[0] += rho * K.gx;
+    F[1] += rho * K.gy;
+    F[2] += rho * K.gz;
+    Real itau, srcg, theta;
+    if (K.const_tau) {
+      itau = K.itau_g;
+      srcg = K.src_g;
+      theta = K.theta_g;
+    } else {
+      Real mu = K.ma;
+#pragma unroll
+      for (int i = 0; i < M; ++i) mu += K.mA[i] * phi[i];
+      const Real tm = Real(3) * mu / rho;  // tau_g - 1/2 (eq:N21_1)
+      itau = Real(1) / (Real(0.5) + tm);
+      srcg = Real(1) - Real(0.5) * itau;
+      theta = Real(1) / tm;
+    }
+    const Real(&g)[15] = P.g;
+    Real m[3] = {Real(0), Real(0), Real(0)}, sumg = Real(0);
+#pragma unroll
+    for (int k = 1; k < 15; ++k) {
+      if (ex3(k)) m[0] += Real(ex3(k)) * g[k];
+      if (ey3(k)) m[1] += Real(ey3(k)) * g[k];
+      if (ez3(k)) m[2] += Real(ez3(k)) * g[k];
+      sumg += g[k];
+    }
+    const Real irho = Real(1) / rho;
+    Real u[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) u[d] = (m[d] + Real(0.5) * F[d]) * irho;  // eq:N22_1
+    const Real usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const Real udr = u[0] * gr[0] + u[1] * gr[1] + u[2] * gr[2];
+    // eq:N23 with w_0 = 2/9: c_s^2 / (1 - w_0) = 3/7, rho s_0 = -(1/3) rho |u|^2
+    const Real p = Real(3) / Real(7) * (sumg + Real(0.5) * udr - Real(1) / Real(3) * rho * usq);
+    const Real uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+    const Real Ju = J[0] * u[0] + J[1] * u[1] + J[2] * u[2];
+    // isotropic part of eq:N20_1: u.grad(rho) - tr(T) / (2 c_s^2)
+    const Real gbase = udr - Real(1.5) * (Real(2) * uF + Real(2) / Real(3) * udr + theta * Ju);
+    if (!lane_int) return;
+    const int rowd = zp * ny + yc;
+    const Rsrc wh = row_rsrc(hd, rbh, rowd), wg = row_rsrc(gd, rbg, rowd),
+               wp = row_rsrc(pvd, rbp, rowd);
+#pragma unroll
+    for (int k = 1; k < 15; ++k) {
+      const Real cx = Real(ex3(k)), cy = Real(ey3(k)), cz = Real(ez3(k));
+      const Real w = w3<Real>(k);
+      const Real cu = cx * u[0] + cy * u[1] + cz * u[2];
+      const Real cF = cx * F[0] + cy * F[1] + cz * F[2];
+      const Real cr = cx * gr[0] + cy * gr[1] + cz * gr[2];
+      const Real cJ = cx * J[0] + cy * J[1] + cz * J[2];
+      const Real geq =
+          w * (Real(3) * p + rho * (Real(3) * cu + Real(4.5) * cu * cu - Real(1.5) * usq));
+      const Real G = w * (gbase + Real(3) * cF +
+                          Real(4.5) * cu * (Real(2) * cF + Real(2) / Real(3) * cr + theta * cJ));
+      bst<Real>(wg, xcu, (uint32_t)(k - 1) * pb, g[k] - itau * (g[k] - geq) + srcg * G);
+    }
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      if constexpr (decltype(kLate)::value) {
+        asm volatile("" ::: "memory");
+        pull_phase(mC, i, P);
+      }
+      const Real pp = P.hi[i];
+      Real ps[3], dd[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        ps[d] = phi[i] * u[d];
+        dd[d] = ps[d] - pp * P.pu[d];  // eq:N27
+      }
+      const Real ec = K.eta_i[i] * Cv[i];
+      const Real it = K.itau_i[i], sr = K.src_i[i];
+      Real hsum = Real(0);
+#pragma unroll
+      for (int k = 1; k < 15; ++k) {
+        const Real cx = Real(ex3(k)), cy = Real(ey3(k)), cz = Real(ez3(k));
+        const Real w = w3<Real>(k);
+        const Real heq = w * (ec + Real(3) * (cx * ps[0] + cy * ps[1] + cz * ps[2]));  // eq:N25
+        const Real R = sr * w * Real(3) * (cx * dd[0] + cy * dd[1] + cz * dd[2]);     // eq:N26
+        const Real hn = P.h[i][k] - it * (P.h[i][k] - heq) + R;
+        hsum += hn;
+        bst<Real>(wh, xcu, (uint32_t)(i * 15 + k) * pb, hn);
+      }
+      // phi_i = pp + lo exactly; fl(phi_i) is stored as the new previous
+      // phi and the k = 0 slot keeps (pp + lo - fl(phi_i)) - sum h_k
+      Real lo = P.h[i][0];
+#pragma unroll
+      for (int k = 1; k < 15; ++k) lo += P.h[i][k];
+      const Real bb = phi[i] - pp;
+      const Real err = (pp - (phi[i] - bb)) + (lo - bb);
+      bst<Real>(wh, xcu, (uint32_t)(i * 15) * pb, err - hsum);
+      bst<Real>(wp, xcu, (uint32_t)i * pb, phi[i]);
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) bst<Real>(wp, xcu, (uint32_t)(M + d) * pb, u[d]);
+  };
+
+  // March: iteration j pulls plane mA = j - 2, computes C of mA - 1 and
+  // collides mA - 2, so J = H + 4 iterations cover the interior planes.
+  // The collision's own pulls are issued before stage A where the registers
+  // allow it (held through two barriers); FP64 with N >= 4 would spill, so
+  // there they are issued at the collision.
+  constexpr bool kEarly = !(sizeof(Real) == 8 && N >= 4);
+  const int J = H + 4;
+  for (int j = 0; j < J; ++j) {  // j is uniform over the block
+    const int mA = j - 2;
+    const int mC = mA - 2;
+    const bool collide = row_int && mC >= 0 && mC < H;  // uniform
+    Col3<M, Real> col;
+    if constexpr (kEarly)
+      if (collide) pull_col(mC, col);
+    stageA(mA);
+    __syncthreads();
+    stageB(mA - 1);
+    __syncthreads();
+    if (collide) stageC(mC, col, std::integral_constant<bool, !kEarly>());
+  }
+}
+
+template <int N, int TY>
+constexpr int lds3_bytes(int bytes) {
+  return (k3PR + k3CR) * (N - 1) * TY * k3W * bytes;
+}
+
+template <int N, int TY>
+hipError_t launch3(int precision, const StepArgs &a, int nblocks, hipStream_t st) {
+  if (precision == 64) {
+    if constexpr (lds3_bytes<N, TY>(8) <= 160 * 1024)
+      hipLaunchKernelGGL((k_step3<N, double, TY>), dim3(nblocks), dim3(k3W * TY), 0, st, a);
+    else
+      return hipErrorInvalidValue;
+  } else {
+    if constexpr (lds3_bytes<N, TY>(4) <= 160 * 1024)
+      hipLaunchKernelGGL((k_step3<N, float, TY>), dim3(nblocks), dim3(k3W * TY), 0, st, a);
+    else
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int N, int TY>
+int occ3(int precision) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+  if (precision == 64) {
+    if constexpr (lds3_bytes<N, TY>(8) <= 160 * 1024)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step3<N, double, TY>, k3W * TY, 0);
+  } else {
+    if constexpr (lds3_bytes<N, TY>(4) <= 160 * 1024)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step3<N, float, TY>, k3W * TY, 0);
+  }
+  return e == hipSuccess ? nb : 0;
+}
+
+}  // namespace
+
+// Rows of the tile: 16 (1024 threads, at most 128 registers each) where
+// that compiles without spills -- FP32 with N <= 3 -- else 8.
+int step3_ty(int N, int precision) {
+  if (const char *e = std::getenv("NPLBM_TY3")) {
+    const int t = std::atoi(e);
+    if (t == 8 || t == 16) return t;
+  }
+  return (precision == 32 && N <= 3) ? 16 : 8;
+}
+
+hipError_t launch_step3(int N, int precision, int ty, const StepArgs &a, int nblocks,
+                        hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  if (ty == 16) {
+    switch (N) {
+      case 2: return launch3<2, 16>(precision, a, nblocks, st);
+      case 3: return launch3<3, 16>(precision, a, nblocks, st);
+      case 4: return launch3<4, 16>(precision, a, nblocks, st);
+      case 5: return launch3<5, 16>(precision, a, nblocks, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (N) {
+    case 2: return launch3<2, 8>(precision, a, nblocks, st);
+    case 3: return launch3<3, 8>(precision, a, nblocks, st);
+    case 4: return launch3<4, 8>(precision, a, nblocks, st);
+    case 5: return launch3<5, 8>(precision, a, nblocks, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int step3_blocks_per_cu(int N, int precision, int ty) {
+  if (ty == 16) {
+    switch (N) {
+      case 2: return occ3<2, 16>(precision);
+      case 3: return occ3<3, 16>(precision);
+      case 4: return occ3<4, 16>(precision);
+      case 5: return occ3<5, 16>(precision);
+      default: return 0;
+    }
+  }
+  switch (N) {
+    case 2: return occ3<2, 8>(precision);
+    case 3: return occ3<3, 8>(precision);
+    case 4: return occ3<4, 8>(precision);
+    case 5: return occ3<5, 8>(precision);
+    default: return 0;
+  }
+}
+
+}  // namespace nplbm

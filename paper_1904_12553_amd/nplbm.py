@@ -52,7 +52,8 @@ class Params(ctypes.Structure):
                 ("mobility", ctypes.POINTER(ctypes.c_double)),
                 ("tau_phi", ctypes.POINTER(ctypes.c_double)),
                 ("interface_width", ctypes.c_double),
-                ("gx", ctypes.c_double), ("gy", ctypes.c_double)]
+                ("gx", ctypes.c_double), ("gy", ctypes.c_double),
+                ("gz", ctypes.c_double), ("nz", ctypes.c_int32), ("wall_z", ctypes.c_int32)]
 
 
 _LIB = None
@@ -117,8 +118,10 @@ def _dp(a: Optional[np.ndarray]):
 
 
 def make_params(N, nx, ny, sigma, rho, mu, mobility=0.1, tau_phi=0.8, W=4.0, wall_y=False,
-                gx=0.0, gy=0.0, precision=64, grad_scheme=0, force_form=0):
-    """Build a Params struct; returns (struct, keepalive arrays)."""
+                gx=0.0, gy=0.0, precision=64, grad_scheme=0, force_form=0, nz=1, wall_z=False,
+                gz=0.0):
+    """Build a Params struct; returns (struct, keepalive arrays).  nz >= 4
+    makes a 3-D (D3Q15) domain."""
     arr = lambda x, n: np.ascontiguousarray(np.broadcast_to(np.asarray(x, np.float64), (n,)))
     sig = np.ascontiguousarray(np.asarray(sigma, np.float64).reshape(N, N))
     keep = (sig, arr(rho, N), arr(mu, N), arr(mobility, N - 1), arr(tau_phi, N - 1))
@@ -126,7 +129,8 @@ def make_params(N, nx, ny, sigma, rho, mu, mobility=0.1, tau_phi=0.8, W=4.0, wal
                grad_scheme=int(grad_scheme), force_form=int(force_form), sigma=_dp(keep[0]),
                rho=_dp(keep[1]),
                mu=_dp(keep[2]), mobility=_dp(keep[3]), tau_phi=_dp(keep[4]),
-               interface_width=float(W), gx=float(gx), gy=float(gy))
+               interface_width=float(W), gx=float(gx), gy=float(gy), gz=float(gz),
+               nz=int(nz), wall_z=int(bool(wall_z)))
     return p, keep
 
 
@@ -174,6 +178,8 @@ class Domain:
     def __init__(self, device: str = "cuda:0", stream=None, **kw):
         torch = _torch()
         self.N, self.nx, self.ny = int(kw["N"]), int(kw["nx"]), int(kw["ny"])
+        self.nz = int(kw.get("nz", 1))
+        self.dim = 3 if self.nz > 1 else 2
         self.precision = int(kw.get("precision", 64))
         self._p, self._keep = make_params(**kw)
         L = lib()
@@ -206,15 +212,21 @@ class Domain:
 
     @property
     def n(self):
-        return self.nx * self.ny
+        return self.nx * self.ny * max(self.nz, 1)
+
+    @property
+    def shape(self):
+        """Shape of one field: (ny, nx) in 2-D, (nz, ny, nx) in 3-D."""
+        return (self.nz, self.ny, self.nx) if self.dim == 3 else (self.ny, self.nx)
 
     @property
     def handle(self):
         return self._h
 
     def set_fields(self, c, u=None):
-        c = np.ascontiguousarray(c, np.float64).reshape(self.N, self.ny, self.nx)
-        u = None if u is None else np.ascontiguousarray(u, np.float64).reshape(2, self.ny, self.nx)
+        c = np.ascontiguousarray(c, np.float64).reshape((self.N,) + self.shape)
+        u = None if u is None else np.ascontiguousarray(u, np.float64).reshape(
+            (self.dim,) + self.shape)
         _check(lib().nplbm_set_fields(self._h, _dp(c), _dp(u)))
 
     def step(self, n: int = 1):
@@ -228,17 +240,17 @@ class Domain:
         return int(lib().nplbm_time(self._h))
 
     def get_c(self):
-        out = np.empty((self.N, self.ny, self.nx))
+        out = np.empty((self.N,) + self.shape)
         _check(lib().nplbm_get_c(self._h, _dp(out)))
         return out
 
     def get_u(self):
-        out = np.empty((2, self.ny, self.nx))
+        out = np.empty((self.dim,) + self.shape)
         _check(lib().nplbm_get_u(self._h, _dp(out)))
         return out
 
     def get_p(self):
-        out = np.empty((self.ny, self.nx))
+        out = np.empty(self.shape)
         _check(lib().nplbm_get_p(self._h, _dp(out)))
         return out
 

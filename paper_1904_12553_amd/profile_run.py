@@ -1,10 +1,13 @@
 """Small driver for rocprofv3 runs (kernel traces and HBM counters).
 
     python3 -m paper_1904_12553_amd.profile_run --what step --steps 10
+    python3 -m paper_1904_12553_amd.profile_run --what step3d --n3 5 --steps 10
     python3 -m paper_1904_12553_amd.profile_run --what copy --mib 1024
 
 ``step`` runs the benchmark workload (N=5, 2048 x 2048, FP32, the same
-launch configuration as bench.py) for a few eager steps; ``copy`` runs the
+launch configuration as bench.py) for a few eager steps; ``step3d`` the
+D3Q15 workloads of the benchmark (256^3, N = 5 slabs and spheres or the
+N = 3 static sphere); ``copy`` runs the
 library's plain copy kernel over a buffer of known size, whose FETCH_SIZE /
 WRITE_SIZE readings calibrate the counters, and prints the copy bandwidth
 measured with HIP events.
@@ -21,7 +24,8 @@ if ROOT not in sys.path:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--what", choices=["step", "copy"], default="step")
+    ap.add_argument("--what", choices=["step", "step3d", "copy"], default="step")
+    ap.add_argument("--n3", type=int, default=5, help="phases of the 3-D workload (3 or 5)")
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--side", type=int, default=2048)
     ap.add_argument("--precision", type=int, default=32)
@@ -50,13 +54,17 @@ def main():
         ms = e0.elapsed_time(e1) / reps
         print(json.dumps({"copy_bytes": n, "ms": ms, "GBps_read_plus_write": 2 * n / ms / 1e6}))
         return
-    w = W.bands_and_droplets(args.side, accept=P.accepts)
+    if args.what == "step3d":
+        w = (W.slabs_and_spheres(256, accept=P.accepts) if args.n3 == 5
+             else W.static_sphere(256, R=64.0))
+    else:
+        w = W.bands_and_droplets(args.side, accept=P.accepts)
     d = P.Domain(precision=args.precision, **w.params())
     d.set_fields(w.c, w.u)
     os.environ["NPLBM_NO_GRAPH"] = "1"
     d.step(args.steps)
     d.sync()
-    print(json.dumps({"steps": args.steps, "nodes": w.nx * w.ny, "N": w.N,
+    print(json.dumps({"steps": args.steps, "nodes": d.n, "N": w.N,
                       "precision": args.precision}))
 
 

@@ -113,3 +113,33 @@ def test_footprint_scales_with_precision_and_size():
     assert nb.footprint(precision=32, **big) > 1.8 * f32
     bad = dict(w.params(), rho=np.array([1.0, 0.0, 1.0]))
     assert nb.footprint(precision=32, **bad) == 0
+
+
+def test_validate_three_dimensional_domains():
+    """nz >= 4 selects the D3Q15 lattice: N <= 5, central stencils, the
+    eq:N20_1 force, periodic y; nz of 2 or 3 is rejected, and wall_z / gz
+    need a 3-D domain."""
+    nb = _lib()
+    sig, rho = W.uniform_sigma(3, 1e-3), np.ones(3)
+    assert nb.footprint(N=3, nx=16, ny=12, nz=8, sigma=sig, rho=rho, mu=np.ones(3)) > 0
+    bad = [dict(nz=2), dict(nz=3), dict(nz=-1), dict(nz=8, grad_scheme=1), dict(nz=8, force_form=1),
+           dict(nz=8, wall_y=True), dict(nz=1, wall_z=True), dict(nz=1, gz=1e-5)]
+    for kw in bad:
+        assert nb.footprint(N=3, nx=16, ny=12, sigma=sig, rho=rho, mu=np.ones(3), **kw) == 0, kw
+    s6 = W.uniform_sigma(6, 1e-3)
+    assert nb.footprint(N=6, nx=16, ny=12, nz=8, sigma=s6, rho=np.ones(6), mu=np.ones(6)) == 0
+
+
+def test_footprint_counts_the_state_of_both_lattices():
+    """Persistent state per node: 10 N values in 2-D (9 (N-1) CH, 8 NS,
+    N + 1 previous) and 16 N + 1 in 3-D (15 (N-1), 14, N + 2), twice for
+    ping-pong, plus FP64 read-back planes."""
+    nb = _lib()
+    for N in (3, 5):
+        sig, rho, mu = W.uniform_sigma(N, 1e-3), np.ones(N), np.ones(N)
+        n2 = nb.footprint(N=N, nx=256, ny=256, sigma=sig, rho=rho, mu=mu, precision=32)
+        n3 = nb.footprint(N=N, nx=64, ny=64, nz=16, sigma=sig, rho=rho, mu=mu, precision=32)
+        nodes = 256 * 256
+        state2, state3 = 2 * 10 * N * 4 * nodes, 2 * (16 * N + 1) * 4 * nodes
+        assert state2 < n2 < state2 * 1.05 + (4 * N + 6) * 8 * nodes
+        assert state3 < n3 < state3 * 1.05 + (4 * N + 8) * 8 * nodes

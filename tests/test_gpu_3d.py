@@ -1,0 +1,101 @@
+"""The D3Q15 (3-D) step on the HIP path, through the C ABI (nz >= 4): FP64
+parity with the 3-D oracle (1e-10 max-abs on c, u, p) over sizes that span
+several tiles with ragged tails in x, y and z, periodic and wall-bounded in
+z; tiny domains smaller than one tile; the graph path with variable tau_g and
+a body force; FP32 against FP64 (1e-5 on c); per-phase mass conservation;
+and the Laplace law of a sphere (Delta p = 2 sigma / R) on a larger box."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import OracleSim3D
+from oracle.accept import oracle_accepts
+from tests.gpu_util import gpu_domain, maxabs
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def _oracle(w, steps):
+    o = OracleSim3D(**w.params())
+    o.init(w.c, w.u)
+    o.step(steps)
+    return o
+
+
+def _parity(w, steps, precision=64):
+    print(f"case {w.name} wall_z={w.wall_z} steps={steps}", flush=True)
+    o = _oracle(w, steps)
+    d = gpu_domain(w, precision=precision)
+    d.step(steps)
+    res = [maxabs(a, b) for a, b in zip(d.macro(), o.macro())]
+    d.close()
+    return res
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 5])
+@pytest.mark.parametrize("wall", [False, True])
+def test_3d_random_parity(N, wall):
+    w = W.random_smooth3d(N, 130, 40, 20, seed=500 + N + 10 * wall, wall_z=wall,
+                          accept=oracle_accepts)
+    assert max(_parity(w, 30)) < TOL
+
+
+@pytest.mark.parametrize("n,wall", [((7, 5, 4), True), ((9, 6, 5), False), ((64, 12, 6), True)])
+def test_3d_tiny_parity(n, wall):
+    w = W.random_smooth3d(3, *n, seed=520 + n[0], wall_z=wall, accept=oracle_accepts)
+    assert max(_parity(w, 25)) < TOL
+
+
+def test_3d_graph_path_and_variable_tau():
+    # >= 64 steps (graph replay), unequal mu / rho, body force in all axes
+    w = W.random_smooth3d(3, 48, 36, 24, seed=531, wall_z=True, accept=oracle_accepts)
+    assert max(_parity(w, 130)) < TOL
+
+
+@pytest.mark.parametrize("N", [3, 5])
+def test_3d_fp32_vs_fp64(N):
+    w = W.random_smooth3d(N, 96, 64, 32, seed=540 + N, wall_z=True, accept=oracle_accepts)
+    a = gpu_domain(w, precision=64)
+    b = gpu_domain(w, precision=32)
+    a.step(300)
+    b.step(300)
+    ca, _, _ = a.macro()
+    cb, _, _ = b.macro()
+    a.close()
+    b.close()
+    assert maxabs(ca, cb) < 1e-5
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_3d_mass_conserved(precision):
+    w = W.random_smooth3d(4, 80, 48, 40, seed=550, wall_z=True, accept=oracle_accepts)
+    d = gpu_domain(w, precision=precision)
+    m0, _, _ = d.diagnostics()
+    d.step(1000)
+    m1, dev, bad = d.diagnostics()
+    d.close()
+    assert bad == 0
+    assert dev < (1e-12 if precision == 64 else 1e-5)
+    assert np.max(np.abs(m1 - m0) / m0) < (1e-12 if precision == 64 else 1e-6)
+
+
+def test_3d_laplace_sphere():
+    """Delta p R / (2 sigma) -> 1 for a sphere of R = 16 in a 64^3 box (the
+    oracle's own 32^3, R = 8 case is pinned on the CPU); FP32 within 0.5% of
+    FP64."""
+    w = W.static_sphere(64, R=16.0)
+    res = {}
+    for prec in (64, 32):
+        d = gpu_domain(w, precision=prec)
+        d.step(3000)
+        c, u, p = d.macro()
+        d.close()
+        x, y, z = W.grid3(64, 64, 64)
+        r = np.sqrt((x - 32) ** 2 + (y - 32) ** 2 + (z - 32) ** 2)
+        R = (3 * c[1].sum() / (4 * np.pi)) ** (1 / 3)
+        dp = p[r < R - 8].mean() - p[r > R + 8].mean()
+        res[prec] = dp * R / (2 * 1e-3)
+        print(f"fp{prec}: R = {R:.3f}, dp R / 2 sigma = {res[prec]:.4f}, max|u| = {np.abs(u).max():.2e}")
+    assert abs(res[64] - 1) < 0.03
+    assert abs(res[32] / res[64] - 1) < 5e-3

@@ -64,8 +64,15 @@ class Workload:
     precision: int = 64
     note: str = ""
     grad_scheme: int = 0        # 0: eq:N31a central, 1: eq:N40 mixed
+    nz: int = 1                 # > 1: a 3-D (D3Q15) workload, fields (.., nz, ny, nx)
+    wall_z: bool = False        # 3-D: walls below plane 0 and above plane nz - 1
+    gz: float = 0.0
 
     def params(self) -> dict:
+        if self.nz > 1:
+            return dict(N=self.N, nx=self.nx, ny=self.ny, nz=self.nz, sigma=self.sigma,
+                        rho=self.rho, mu=self.mu, mobility=self.mobility, tau_phi=self.tau_phi,
+                        W=self.W, wall_z=self.wall_z, gx=self.gx, gy=self.gy, gz=self.gz)
         return dict(N=self.N, nx=self.nx, ny=self.ny, sigma=self.sigma, rho=self.rho,
                     mu=self.mu, mobility=self.mobility, tau_phi=self.tau_phi, W=self.W,
                     wall_y=self.wall_y, gx=self.gx, gy=self.gy, grad_scheme=self.grad_scheme)
@@ -346,6 +353,109 @@ def random_smooth(N: int, nx: int, ny: int, seed: int, wall_y: bool = False,
                     mobility=float(rng.uniform(0.05, 0.2)), tau_phi=float(rng.uniform(0.7, 1.2)),
                     W=W, wall_y=wall_y, gx=float(rng.uniform(-1e-5, 1e-5)),
                     gy=float(rng.uniform(-1e-5, 1e-5)))
+
+
+# ---------------------------------------------------------------------------
+# Three-dimensional (D3Q15) workloads
+# ---------------------------------------------------------------------------
+
+def grid3(nx: int, ny: int, nz: int):
+    z, y, x = np.mgrid[0:nz, 0:ny, 0:nx].astype(np.float64)
+    return x, y, z
+
+
+def random_smooth3d(N: int, nx: int, ny: int, nz: int, seed: int, wall_z: bool = False,
+                    amp_u: float = 1e-2, accept=None, W: float = 4.0,
+                    unequal: bool = True) -> Workload:
+    """3-D counterpart of random_smooth: N smooth random non-negative
+    fractions summing to one, a smooth random velocity (3 components),
+    random tensions, densities in [1, 3], per-phase viscosities and a small
+    body force."""
+    rng = np.random.default_rng(seed)
+    x, y, z = grid3(nx, ny, nz)
+    fields = []
+    for _ in range(N):
+        a = np.zeros((nz, ny, nx))
+        for _ in range(3):
+            kx, ky, kz = rng.integers(0, 3, size=3)
+            ph = rng.uniform(0, 2 * np.pi)
+            a += rng.uniform(0.2, 1.0) * np.cos(
+                2 * np.pi * (kx * x / nx + ky * y / ny + kz * z / nz) + ph)
+        fields.append(np.exp(1.5 * a))
+    tot = sum(fields)
+    c = np.stack([f / tot for f in fields[:-1]])
+    c = np.concatenate([c, (1.0 - c.sum(axis=0))[None]])
+    u = np.zeros((3, nz, ny, nx))
+    for d in range(3):
+        kx, ky, kz = rng.integers(1, 3, size=3)
+        ph = rng.uniform(0, 2 * np.pi)
+        u[d] = amp_u * np.sin(2 * np.pi * (kx * x / nx + ky * y / ny + kz * z / nz) + ph)
+    rho = rng.uniform(1.0, 3.0, size=N) if unequal else np.ones(N)
+    sigma, _ = draw_sigma(N, seed + 1, accept=accept, rho=rho)
+    mu = rng.uniform(0.05, 0.3, size=N) * rho
+    return Workload(f"random3d_N{N}_{nx}x{ny}x{nz}", N, nx, ny, sigma, rho, mu, c, u,
+                    mobility=float(rng.uniform(0.05, 0.2)), tau_phi=float(rng.uniform(0.7, 1.2)),
+                    W=W, gx=float(rng.uniform(-1e-5, 1e-5)), gy=float(rng.uniform(-1e-5, 1e-5)),
+                    nz=nz, wall_z=wall_z, gz=float(rng.uniform(-1e-5, 1e-5)))
+
+
+def static_sphere(n: int = 64, R: float = 16.0, W: float = 4.0, sigma: float = 1e-3,
+                  tau_g: float = 1.0, precision: int = 64, steps: int = 2000) -> Workload:
+    """3-D counterpart of static_droplet: N=3, a phase-2 sphere of radius R at
+    the centre of a periodic n^3 box of phase 1, phase 3 absent, equal
+    densities, viscosity for tau_g."""
+    x, y, z = grid3(n, n, n)
+    r = np.sqrt((x - n / 2.0) ** 2 + (y - n / 2.0) ** 2 + (z - n / 2.0) ** 2)
+    c2 = _profile(R - r, W)
+    c3 = np.zeros_like(c2)
+    nu = (tau_g - 0.5) / 3.0
+    return Workload("static_sphere_N3", 3, n, n, uniform_sigma(3, sigma), np.ones(3),
+                    np.full(3, nu), np.stack([1.0 - c2, c2, c3]), None, mobility=0.1,
+                    tau_phi=0.8, W=W, steps=steps, precision=precision, nz=n)
+
+
+def slabs_and_spheres(side: int = 256, ndrop: int = 64, W: float = 4.0,
+                      seed: int = BASE_SEED + 5, accept=None, precision: int = 32,
+                      steps: int = 20000, rmin: float = 6.0, rmax: float = 20.0) -> Workload:
+    """3-D counterpart of bands_and_droplets: N=5 in a periodic side^3 box;
+    slabs of phases 1, 2, 3 of thickness side/4 stacked in z from z = side/8
+    (phase 4 fills the rest), plus ``ndrop`` phase-5 spheres with radius ~
+    U[rmin, rmax] at seeded, non-overlapping centres (gap >= 2W); sigma_kl ~
+    U[0.5e-3, 2e-3], rho_k ~ U[1, 3], mu_k = 0.1 rho_k."""
+    z = np.arange(side, dtype=np.float64)[:, None, None]
+    h, z0 = side / 4.0, side / 8.0
+    slabs = [np.broadcast_to(0.5 * (np.tanh(2.0 * (z - (z0 + b * h)) / W)
+                                    - np.tanh(2.0 * (z - (z0 + (b + 1) * h)) / W)),
+                             (side, side, side)) for b in range(3)]
+    rng = np.random.default_rng(seed)
+    drops: List[tuple] = []
+    tries = 0
+    while len(drops) < ndrop:
+        tries += 1
+        if tries > 200000:
+            raise RuntimeError("could not place spheres")
+        r = rng.uniform(rmin, rmax)
+        cen = rng.uniform(r + W, side - r - W, size=3)
+        if all(np.linalg.norm(cen - np.array(d[:3])) >= r + d[3] + 2 * W for d in drops):
+            drops.append((cen[0], cen[1], cen[2], r))
+    c5 = np.zeros((side, side, side))
+    for xc, yc, zc, r in drops:
+        lo = [int(max(0, v - r - 4 * W)) for v in (xc, yc, zc)]
+        hi = [int(min(side, v + r + 4 * W + 1)) for v in (xc, yc, zc)]
+        zz, yy, xx = np.mgrid[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].astype(np.float64)
+        d = r - np.sqrt((xx - xc) ** 2 + (yy - yc) ** 2 + (zz - zc) ** 2)
+        c5[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] += _profile(d, W)
+    np.minimum(c5, 1.0, out=c5)
+    keep = 1.0 - c5
+    phases = [s_ * keep for s_ in slabs]
+    c4 = 1.0 - phases[0] - phases[1] - phases[2] - c5
+    c = np.stack(phases + [c4, c5])
+    rng2 = np.random.default_rng(seed + 1000)
+    rho = rng2.uniform(1.0, 3.0, size=5)
+    sigma, redraws = draw_sigma(5, seed + 7, accept=accept, rho=rho)
+    return Workload("slabs_spheres_N5", 5, side, side, sigma, rho, 0.1 * rho, c, None,
+                    mobility=0.1, tau_phi=0.8, W=W, steps=steps, precision=precision,
+                    nz=side, note=f"sigma redraws={redraws}; spheres={len(drops)}")
 
 
 # ---------------------------------------------------------------------------
