@@ -38,6 +38,7 @@ struct Layout {
   size_t desc = 0, strips = 0;
   int nstrips = 0;
   size_t phi = 0, rho = 0, C = 0, c = 0, u = 0, p = 0, q = 0;
+  size_t phi3 = 0;  // 3-D: phi array of the step (state precision)
   int nblk = 0;
   size_t partials = 0, out = 0;
   size_t total = 0;

@@ -46,7 +46,9 @@ double *dptr(nplbm_domain *d, size_t off) { return reinterpret_cast<double *>(d-
 size_t nnodes(const nplbm_domain *d) { return (size_t)d->p.nx * d->p.ny * dom_nz(&d->p); }
 
 hipError_t launch_any_step(nplbm_domain *d, const StepArgs &a) {
-  if (d->d3) return launch_step3(d->p.N, d->p.precision, d->ty, a, d->nstrips, d->stream);
+  if (d->d3)
+    return launch_step3(d->p.N, d->p.precision, d->ty, a, d->nstrips, d->p.nx, d->p.ny, d->p.nz,
+                        d->stream);
   return launch_step(d->p.N, d->p.precision, step_scheme(&d->p), d->geom.bw, a, d->nstrips,
                      d->stream);
 }
@@ -226,6 +228,10 @@ int nplbm_create(const nplbm_params *p, void *stream, void *device_mem, size_t d
   D.nx = p->nx;
   D.ny = p->ny;
   D.nz = dom_nz(p);
+  if (is3d(p)) {
+    D.phi3 = d->base + d->L.phi3;
+    D.rsf = (N - 1) * d->L.pitch;
+  }
   D.pitch = d->L.pitch;
   D.wall = is3d(p) ? p->wall_z : p->wall_y;
   D.N = N;

@@ -105,6 +105,11 @@ int derive(const nplbm_params *p, Derived &d) {
     if (p->wall_y != 0) return fail(NPLBM_EINVAL, "3-D domains are periodic in y (wall_y 0)");
     if (p->wall_z != 0 && p->wall_z != 1) return fail(NPLBM_EINVAL, "wall_z must be 0 or 1");
     if (!std::isfinite(p->gz)) return fail(NPLBM_EINVAL, "gz must be finite");
+    // the 3-D kernel addresses one plane of a state group (ny row blocks)
+    // with 32-bit byte offsets below 2^31
+    if ((int64_t)p->ny * 15 * (N - 1) * (((int64_t)p->nx + 31) & ~(int64_t)31) *
+            (p->precision / 8) >= (int64_t)1 << 31)
+      return fail(NPLBM_EINVAL, "nx * ny too large for a 3-D domain: a plane would exceed 2^31 bytes");
   } else if (p->wall_z != 0 || p->gz != 0.0) {
     return fail(NPLBM_EINVAL, "wall_z and gz apply to 3-D domains (nz >= 4) only");
   }
@@ -417,6 +422,8 @@ Layout plan_layout(const nplbm_params *p) {
   L.c = take((size_t)N * n * 8);
   L.u = take((d3 ? 3 : 2) * n * 8);
   L.p = take(n * 8);
+  // 3-D: the phi array written by the phi pass of each step
+  L.phi3 = d3 ? take((size_t)nrows * M * L.pitch * s) : 0;
   // the products J~_b u_a of the Remark 1 force, for the read-back
   L.q = p->force_form == 1 ? take(4 * n * 8) : 0;
   L.nblk = diag_blocks((int64_t)n);
@@ -515,10 +522,10 @@ void xcd_order(std::vector<StripDesc> &s) {
 }
 
 // Tile decomposition of a 3-D domain for the marching 3-D step kernel:
-// tiles of at most 60 x (ty - 4) interior nodes in (x, y), as equal as
-// possible, each marching through nz / nsz planes, nsz chosen so that the
-// launch has about `target` workgroups; neighbouring z segments march in
-// opposite directions.
+// tiles of 64 columns starting on multiples of 64 (the last one ragged) and
+// at most ty - 4 rows, rows split as equally as possible, each marching
+// through nz / nsz planes, nsz chosen so that the launch has about `target`
+// workgroups; neighbouring z segments march in opposite directions.
 void build_tiles3(int nx, int ny, int nz, int dom, int ty, int target,
                   std::vector<StripDesc> &out) {
   auto split = [](int n, int maxw, std::vector<int> &edges) {
@@ -527,7 +534,8 @@ void build_tiles3(int nx, int ny, int nz, int dom, int ty, int target,
     for (int i = 0; i < parts; ++i) edges[i + 1] = edges[i] + n / parts + (i < n % parts ? 1 : 0);
   };
   std::vector<int> xs, ys;
-  split(nx, 60, xs);
+  for (int x = 0; x < nx; x += 64) xs.push_back(x);
+  xs.push_back(nx);
   split(ny, ty - 4, ys);
   const int nxy = (int)((xs.size() - 1) * (ys.size() - 1));
   if (target <= 0) target = 1024;

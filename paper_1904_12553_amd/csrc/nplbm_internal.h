@@ -85,7 +85,11 @@ struct DomDesc {
   // 14 NS planes (k = 1..14) and (N-1) + 3 previous-step planes; `wall`
   // means halfway bounce-back walls below plane 0 and above plane nz - 1.
   int32_t nz;
-  int32_t pad3_;
+  // 3-D: elements per row block of the phi array (M * pitch); the array
+  // holds phi_i of the current state, [(z * ny + y)][i][pitch], written by
+  // the phi pass and read by the step pass of the same time step
+  int32_t rsf;
+  void *phi3;
   Consts<double> cd;
   Consts<float> cf;
 };
@@ -138,8 +142,10 @@ int step_blocks_per_cu_remark1(int N, int precision, int bw);
 // The 3-D (D3Q15) step kernel: tiles of (64 - 4) x (ty - 4) interior nodes,
 // ty rows of one 64-lane wave each (ty = 8 or 16).
 int step3_ty(int N, int precision);
-hipError_t launch_step3(int N, int precision, int ty, const StepArgs &a, int nblocks,
-                        hipStream_t st);
+// One 3-D time step: the phi pass over all nx * ny * nz nodes of domain 0
+// of a.doms, then the tiled step pass over nblocks tiles.
+hipError_t launch_step3(int N, int precision, int ty, const StepArgs &a, int nblocks, int nx,
+                        int ny, int nz, hipStream_t st);
 int step3_blocks_per_cu(int N, int precision, int ty);
 // 3-D initialisation and read-back, the counterparts of launch_init /
 // launch_macro below on dense (nz * ny * nx) planes; u has 3 planes.

@@ -1,5 +1,5 @@
-// step3d_kernel.hip -- one fused time step of the N-phase phase-field LB
-// model (arXiv:1904.12553) on the D3Q15 lattice of Sec. 3.1, for gfx950.
+// step3d_kernel.hip -- one time step of the N-phase phase-field LB model
+// (arXiv:1904.12553) on the D3Q15 lattice of Sec. 3.1, for gfx950.
 //
 // The arithmetic per node is that of the 2-D kernel (step_kernel.hip) with
 // three velocity components: pull streaming, phi_i by eq:N28 (the stored
@@ -9,19 +9,23 @@
 // eq:N23, NS collision eq:24 / eq:25 / eq:N20_1, CH collisions
 // eq:N24-N27.  Only eq:N31a's central stencils and eq:N20_1 are built in 3-D.
 //
-// Work decomposition.  A workgroup owns a tile of interior nodes
-// [x0, x1) x [y0, y1) (at most 60 x (ty - 4)) and marches through the planes
-// [z0, z1).  Its threads cover the tile plus a 2-node halo in x and y: one
-// 64-lane wave per row of the extended tile, ty rows.  Each iteration pulls
-// plane mA (all threads; streaming fused into the load, bounce-back at z
-// walls as a uniform choice), sums phi into a 5-plane LDS ring; computes C
-// of plane mA - 1 on the tile plus a ring of one into a 4-plane LDS ring; and
-// collides plane mA - 2 on the interior.  The populations of the collision
-// plane were already read two iterations earlier for phi; they are read
-// again (from L2 / MALL), issued at the start of the iteration so the loads
-// are in flight during the phi and C stages.  D3Q15 stencils reach the six
-// faces and eight corners of a node, so the halo is two nodes for phi and one
-// for C, as in 2-D.
+// Two passes per step.  The phi pass (k_phi3) pulls the CH populations of
+// every node once -- streaming fused into the load, bounce-back at z walls
+// -- and writes phi_i to a dense array.  The step pass (k_step3) then owns
+// a tile of interior nodes [x0, x1) x [y0, y1) (at most 64 x (ty - 4), x0 a
+// multiple of 64, so loads and stores are whole cache lines) and marches
+// through the planes [z0, z1) with one 64-lane wave per row of the tile plus
+// a 2-row halo, ty rows; four lanes bring in the 2-column halos.  Each iteration copies phi of plane mA
+// from the array into a 5-plane LDS ring (all threads; the next plane's
+// values are loaded right after, so they are in flight during the rest of
+// the iteration); computes C of plane mA - 1 on the tile plus a ring of one
+// into a 4-plane ring; and collides plane mA - 2 on the interior with the
+// populations it pulls for that node, issued at the start of the iteration.
+// The halo rings thus cost (N - 1) reads per node of the phi array (mostly
+// from the 256 MB MALL, where the phi pass left it) instead of 16 (N - 1)
+// population reads, and no population is read twice by the step pass.
+// D3Q15 stencils reach the six faces and eight corners of a node, so the
+// halo is two nodes for phi and one for C, as in 2-D.
 //
 // Stencils on D3Q15 (eq:N31 with the weights 1/9 and 1/72, c_s^2 = 1/3):
 //   lap   = (8 sum_faces + sum_corners - 56 zeta) / 12
@@ -39,7 +43,8 @@ namespace nplbm {
 
 namespace {
 
-constexpr int k3W = 64;   // threads per tile row (one wave)
+constexpr int k3W = 64;   // threads per tile row (one wave) = interior columns of a tile
+constexpr int k3L = 68;   // LDS row: the 64 columns plus 2 halo columns each side
 constexpr int k3PR = 5;   // phi ring planes
 constexpr int k3CR = 4;   // C ring planes
 
@@ -94,21 +99,27 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
   const uint32_t rbh = (uint32_t)D->rs[0] * SZ, rbg = (uint32_t)D->rs[1] * SZ,
                  rbp = (uint32_t)D->rs[2] * SZ;
 
-  __shared__ Real sphi[k3PR][M][TY][k3W];
-  __shared__ Real sC[k3CR][M][TY][k3W];
+  __shared__ Real sphi[k3PR][M][TY][k3L];
+  __shared__ Real sC[k3CR][M][TY][k3L];
 
   const int lane = threadIdx.x & (k3W - 1);
   const int ty = __builtin_amdgcn_readfirstlane(threadIdx.x / k3W);  // uniform
   const int nxi = x1 - x0, nyi = y1 - y0;
-  const int xc = wrap_i(x0 - 2 + lane, nx);
+  // Columns: lane l owns interior column x0 + l (tiles start on whole
+  // cache lines, so every row of loads and stores is line-aligned) at LDS
+  // column l + 2; lanes 0..3 also bring the halo columns x0 - 2, x0 - 1,
+  // x0 + 64, x0 + 65 (LDS columns 0, 1, 66, 67) into the phi ring.
+  const int xc = wrap_i(x0 + lane, nx);
+  const int col = lane + 2;
+  const int hcol = lane < 2 ? lane : 64 + lane;  // halo LDS column (lanes < 4)
+  const uint32_t xh = (uint32_t)wrap_i(lane < 2 ? x0 - 2 + lane : x0 + 62 + lane, nx) * SZ;
   const uint32_t xcu = (uint32_t)xc * SZ;
   const uint32_t xw = (uint32_t)(xc == 0 ? nx - 1 : xc - 1) * SZ;  // x - 1
   const uint32_t xe = (uint32_t)(xc == nx - 1 ? 0 : xc + 1) * SZ;  // x + 1
   const int yc = wrap_i(y0 - 2 + ty, ny);                            // uniform
   const int yS = yc == 0 ? ny - 1 : yc - 1, yN = yc == ny - 1 ? 0 : yc + 1;
-  const bool lane_int = lane >= 2 && lane < 2 + nxi;
+  const bool lane_int = lane < nxi;
   const bool row_int = ty >= 2 && ty < 2 + nyi;                      // uniform
-  const bool lane_r1 = lane >= 1 && lane < 3 + nxi;
   const bool row_r1 = ty >= 1 && ty < 3 + nyi;                       // uniform
   const int H = z1 - z0;
 
@@ -128,116 +139,125 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
   auto ring5 = [](int m) { return (m + 16 * k3PR) % k3PR; };
   auto ring4 = [](int m) { return (m + 16 * k3CR) % k3CR; };
 
-  // Source of population k arriving at (xc, yc, zp): the node x - c_k, or
-  // the node itself with the opposite direction when z - c_z lies beyond a
-  // wall.  Planes and rows are uniform; the column offset is per lane.
-  struct Src {
-    int zp, zS, zN;  // planes zp, zp - 1, zp + 1 (wrapped)
-    bool bS, bN;     // bounce for c_z = +1 / c_z = -1
+  // Addressing.  A buffer resource spans one plane block of a group (its ny
+  // row blocks); the row is a scalar byte offset fixed for the whole march
+  // (the tile's rows do not change), the plane offset another scalar, and
+  // the column the per-lane offset.
+  const uint32_t ybh[3] = {(uint32_t)yS * rbh, (uint32_t)yc * rbh, (uint32_t)yN * rbh};
+  const uint32_t ybg[3] = {(uint32_t)yS * rbg, (uint32_t)yc * rbg, (uint32_t)yN * rbg};
+  const uint32_t ybp = (uint32_t)yc * rbp;
+  const uint32_t plh = (uint32_t)ny * rbh, plg = (uint32_t)ny * rbg, plp = (uint32_t)ny * rbp;
+
+  // Sources of the populations arriving at plane zp: plane zp - c_z, or the
+  // node itself with the opposite direction when that plane lies beyond a
+  // wall (bounce-back).  Index 0 / 1 / 2 = plane zp - 1 / zp / zp + 1.
+  struct Planes {
+    Rsrc r[3];
+    bool bS, bN;  // bounce for c_z = +1 / c_z = -1
   };
-  auto make_src = [&](int zp) {
-    Src s;
-    s.zp = zp;
-    s.bS = wall && zp == 0;
-    s.bN = wall && zp == nz - 1;
-    s.zS = zp == 0 ? nz - 1 : zp - 1;
-    s.zN = zp == nz - 1 ? 0 : zp + 1;
-    return s;
+  auto planes_of = [&](const void *base, uint32_t pl, int zp) {
+    Planes P;
+    P.bS = wall && zp == 0;
+    P.bN = wall && zp == nz - 1;
+    P.r[0] = row_rsrc(base, pl, zp == 0 ? nz - 1 : zp - 1);
+    P.r[1] = row_rsrc(base, pl, zp);
+    P.r[2] = row_rsrc(base, pl, zp == nz - 1 ? 0 : zp + 1);
+    return P;
   };
-  // buffer resource of the row block (plane, row) a population comes from
-  auto src_rsrc = [&](const void *base, uint32_t rb, const Src &s, int k, int &kk,
-                      uint32_t &co) {
+  // load plane q0 + kk of direction k (kk = k, or its opposite when
+  // bounced).  Bounce-back happens only on the two planes next to a wall,
+  // so the callers take a branch-free path (kWall false) everywhere else.
+  auto pull = [&](const Planes &P, const uint32_t (&yb)[3], int k, int q0, auto kWall) {
     const int cx = ex3(k), cy = ey3(k), cz = ez3(k);
-    const bool b = (cz == 1 && s.bS) || (cz == -1 && s.bN);
-    kk = b ? opp3(k) : k;
-    co = b ? xcu : (cx == 1 ? xw : (cx == -1 ? xe : xcu));
-    const int zz = b ? s.zp : (cz == 1 ? s.zS : (cz == -1 ? s.zN : s.zp));
-    const int yy = b ? yc : (cy == 1 ? yS : (cy == -1 ? yN : yc));
-    return row_rsrc(base, rb, zz * ny + yy);
+    const uint32_t col = cx == 1 ? xw : (cx == -1 ? xe : xcu);
+    if (!decltype(kWall)::value || cz == 0)
+      return bld<Real>(P.r[1 - cz], col, yb[1 - cy] + (uint32_t)(q0 + k) * pb);
+    const bool b = cz == 1 ? P.bS : P.bN;
+    const Rsrc r = b ? P.r[1] : P.r[cz == 1 ? 0 : 2];
+    const uint32_t so = b ? yb[1] + (uint32_t)(q0 + opp3(k)) * pb
+                          : yb[1 - cy] + (uint32_t)(q0 + k) * pb;
+    return bld<Real>(r, b ? xcu : col, so);
+  };
+  // run f(kWall) with kWall a compile-time flag: does plane zp border a wall?
+  auto by_wall = [&](const Planes &P, auto f) {
+    if (P.bS || P.bN)
+      f(std::true_type());
+    else
+      f(std::false_type());
   };
 
   // ---- pull what the collision of march index m reads ----
   // CH populations of phase i
-  auto pull_phase = [&](int m, int i, Col3<M, Real> &P) {
-    const int zp = phys_plane(plane_of(m));
-    const Src s = make_src(zp);
+  auto pull_phase = [&](int m, int i, Col3<M, Real> &C) {
+    const Planes P = planes_of(hs, plh, phys_plane(plane_of(m)));
+    by_wall(P, [&](auto kWall) {
 #pragma unroll
-    for (int k = 0; k < 15; ++k) {
-      int kk;
-      uint32_t co;
-      const Rsrc r = src_rsrc(hs, rbh, s, k, kk, co);
-      P.h[i][k] = bld<Real>(r, co, (uint32_t)(i * 15 + kk) * pb);
-    }
+      for (int k = 0; k < 15; ++k) C.h[i][k] = pull(P, ybh, k, i * 15, kWall);
+    });
   };
-  // NS populations, stored previous phi and u
-  auto pull_ns = [&](int m, Col3<M, Real> &P) {
+  // NS populations (planes k - 1), stored previous phi and u
+  auto pull_ns = [&](int m, Col3<M, Real> &C) {
     const int zp = phys_plane(plane_of(m));
-    const Src s = make_src(zp);
+    const Planes P = planes_of(gs, plg, zp);
+    by_wall(P, [&](auto kWall) {
 #pragma unroll
-    for (int k = 1; k < 15; ++k) {
-      int kk;
-      uint32_t co;
-      const Rsrc r = src_rsrc(gs, rbg, s, k, kk, co);
-      P.g[k] = bld<Real>(r, co, (uint32_t)(kk - 1) * pb);
-    }
-    const Rsrc rp = row_rsrc(pvs, rbp, zp * ny + yc);
+      for (int k = 1; k < 15; ++k) C.g[k] = pull(P, ybg, k, -1, kWall);
+    });
+    const Rsrc rp = row_rsrc(pvs, plp, zp);
 #pragma unroll
-    for (int i = 0; i < M; ++i) P.hi[i] = bld<Real>(rp, xcu, (uint32_t)i * pb);
+    for (int i = 0; i < M; ++i) C.hi[i] = bld<Real>(rp, xcu, ybp + (uint32_t)i * pb);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) P.pu[d] = bld<Real>(rp, xcu, (uint32_t)(M + d) * pb);
+    for (int d = 0; d < 3; ++d) C.pu[d] = bld<Real>(rp, xcu, ybp + (uint32_t)(M + d) * pb);
   };
-  auto pull_col = [&](int m, Col3<M, Real> &P) {
+  auto pull_col = [&](int m, Col3<M, Real> &C) {
 #pragma unroll
-    for (int i = 0; i < M; ++i) pull_phase(m, i, P);
-    pull_ns(m, P);
+    for (int i = 0; i < M; ++i) pull_phase(m, i, C);
+    pull_ns(m, C);
   };
 
-  // ---- stage A: phi of march index mA -> LDS (all threads) ----
-  auto stageA = [&](int mA) {
-    const int zp = phys_plane(plane_of(mA));
-    const Src s = make_src(zp);
-    Real lo[M];
+  // ---- stage A: phi of march index mA (from the phi pass) -> LDS ----
+  // all threads; the values of plane mA + 1 are loaded right after, so they
+  // are in flight during the rest of the iteration
+  const uint32_t rbf = (uint32_t)D->rsf * SZ, plf = (uint32_t)ny * rbf;
+  const uint32_t ybf = (uint32_t)yc * rbf;
+  const void *phi3 = D->phi3;
+  auto load_phi = [&](int mA, Real (&f)[M], Real (&fh)[M]) {
+    const Rsrc r = row_rsrc(phi3, plf, phys_plane(plane_of(mA)));
 #pragma unroll
-    for (int i = 0; i < M; ++i) lo[i] = Real(0);
-#pragma unroll
-    for (int k = 0; k < 15; ++k) {
-      int kk;
-      uint32_t co;
-      const Rsrc r = src_rsrc(hs, rbh, s, k, kk, co);
-#pragma unroll
-      for (int i = 0; i < M; ++i) lo[i] += bld<Real>(r, co, (uint32_t)(i * 15 + kk) * pb);
+    for (int i = 0; i < M; ++i) {
+      f[i] = bld<Real>(r, xcu, ybf + (uint32_t)i * pb);
+      fh[i] = bld<Real>(r, xh, ybf + (uint32_t)i * pb);
     }
-    const Rsrc rp = row_rsrc(pvs, rbp, zp * ny + yc);
+  };
+  auto stageA = [&](int mA, const Real (&f)[M], const Real (&fh)[M]) {
     const int slot = ring5(mA);
 #pragma unroll
-    for (int i = 0; i < M; ++i)
-      sphi[slot][i][ty][lane] = bld<Real>(rp, xcu, (uint32_t)i * pb) + lo[i];  // eq:N28
+    for (int i = 0; i < M; ++i) sphi[slot][i][ty][col] = f[i];
+    if (lane < 4)
+#pragma unroll
+      for (int i = 0; i < M; ++i) sphi[slot][i][ty][hcol] = fh[i];
   };
 
   // ---- stage B: chemical potentials of march index mB -> LDS ----
-  // On the tile plus a ring of one.  Planes beyond a wall are skipped: the
-  // collision next to the wall reads its own plane for the mirror ghost.
-  auto stageB = [&](int mB) {
-    if (!row_r1 || !lane_r1) return;
-    if (wall) {
-      const int z = plane_of(mB);
-      if (z < 0 || z >= nz) return;
-    }
-    const int s0 = ring5(mB), sU = ring5(mB + dir), sD = ring5(mB - dir);
+  // On the tile plus a ring of one: LDS columns 1 .. nxi + 2, taken as
+  // lane + 1 and, for the last two, 65 + lane.  Planes beyond a wall are
+  // skipped: the collision next to the wall reads its own plane for the
+  // mirror ghost.
+  auto chem_at = [&](int c, int s0, int sU, int sD, int sc) {
     Real phi[M], lap[M];
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-      const Real c = sphi[s0][i][ty][lane];
-      const Real faces = (sphi[s0][i][ty][lane + 1] + sphi[s0][i][ty][lane - 1]) +
-                         (sphi[s0][i][ty + 1][lane] + sphi[s0][i][ty - 1][lane]) +
-                         (sphi[sU][i][ty][lane] + sphi[sD][i][ty][lane]);
+      const Real v = sphi[s0][i][ty][c];
+      const Real faces = (sphi[s0][i][ty][c + 1] + sphi[s0][i][ty][c - 1]) +
+                         (sphi[s0][i][ty + 1][c] + sphi[s0][i][ty - 1][c]) +
+                         (sphi[sU][i][ty][c] + sphi[sD][i][ty][c]);
       const Real corners =
-          ((sphi[sU][i][ty + 1][lane + 1] + sphi[sU][i][ty + 1][lane - 1]) +
-           (sphi[sU][i][ty - 1][lane + 1] + sphi[sU][i][ty - 1][lane - 1])) +
-          ((sphi[sD][i][ty + 1][lane + 1] + sphi[sD][i][ty + 1][lane - 1]) +
-           (sphi[sD][i][ty - 1][lane + 1] + sphi[sD][i][ty - 1][lane - 1]));
-      lap[i] = (Real(8) * faces + corners - Real(56) * c) * (Real(1) / Real(12));  // eq:N31b
-      phi[i] = c;
+          ((sphi[sU][i][ty + 1][c + 1] + sphi[sU][i][ty + 1][c - 1]) +
+           (sphi[sU][i][ty - 1][c + 1] + sphi[sU][i][ty - 1][c - 1])) +
+          ((sphi[sD][i][ty + 1][c + 1] + sphi[sD][i][ty + 1][c - 1]) +
+           (sphi[sD][i][ty - 1][c + 1] + sphi[sD][i][ty - 1][c - 1]));
+      lap[i] = (Real(8) * faces + corners - Real(56) * v) * (Real(1) / Real(12));  // eq:N31b
+      phi[i] = v;
     }
     Real wv[N];
 #pragma unroll
@@ -247,7 +267,6 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
       for (int i = 0; i < M; ++i) ck += K.cA[k][i] * phi[i];
       wv[k] = ck * (Real(1) - ck) * (Real(1) - Real(2) * ck);
     }
-    const int sc = ring4(mB);
 #pragma unroll
     for (int i = 0; i < M; ++i) {
       Real Ci = Real(0);
@@ -255,13 +274,23 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
       for (int j = 0; j < M; ++j) Ci -= K.lam[i][j] * lap[j];
 #pragma unroll
       for (int k = 0; k < N; ++k) Ci += K.KH[k][i] * wv[k];
-      sC[sc][i][ty][lane] = Ci;
+      sC[sc][i][ty][c] = Ci;
     }
+  };
+  auto stageB = [&](int mB) {
+    if (!row_r1) return;
+    if (wall) {
+      const int z = plane_of(mB);
+      if (z < 0 || z >= nz) return;
+    }
+    const int s0 = ring5(mB), sU = ring5(mB + dir), sD = ring5(mB - dir), sc = ring4(mB);
+    if (lane + 1 <= nxi + 2) chem_at(lane + 1, s0, sU, sD, sc);
+    if (lane < 2 && 65 + lane <= nxi + 2) chem_at(65 + lane, s0, sU, sD, sc);
   };
 
   // eq:N31a on D3Q15 from an LDS ring: planes s0 (own), sU (z + 1), sD (z - 1)
-  // around column `lane` (clamped by the caller to [1, 62])
-  auto grad3 = [&](const Real (*f)[M][TY][k3W], int lane, int s0, int sU, int sD, int i,
+  // around LDS column `lane` (2 .. 65)
+  auto grad3 = [&](const Real (*f)[M][TY][k3L], int lane, int s0, int sU, int sD, int i,
                    Real &gx, Real &gy, Real &gz) {
     const Real upp = f[sU][i][ty + 1][lane + 1], upm = f[sU][i][ty + 1][lane - 1];
     const Real ump = f[sU][i][ty - 1][lane + 1], umm = f[sU][i][ty - 1][lane - 1];
@@ -288,8 +317,9 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
     const int s0 = ring5(mC), c0 = ring4(mC);
     const int sU = gU ? s0 : ring5(mC + dir), sD = gD ? s0 : ring5(mC - dir);
     const int cU = gU ? c0 : ring4(mC + dir), cD = gD ? c0 : ring4(mC - dir);
-    // x-halo lanes compute on clamped columns and do not store
-    const int ln = lane < 1 ? 1 : (lane > k3W - 2 ? k3W - 2 : lane);
+    // lanes past a ragged tile end compute on their (valid) columns and do
+    // not store
+    const int ln = col;
     Real phi[M], Cv[M];
     Real rho = K.ra, gr[3] = {Real(0), Real(0), Real(0)}, F[3] = {Real(0), Real(0), Real(0)},
          J[3] = {Real(0), Real(0), Real(0)};
@@ -347,9 +377,8 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
     // isotropic part of eq:N20_1: u.grad(rho) - tr(T) / (2 c_s^2)
     const Real gbase = udr - Real(1.5) * (Real(2) * uF + Real(2) / Real(3) * udr + theta * Ju);
     if (!lane_int) return;
-    const int rowd = zp * ny + yc;
-    const Rsrc wh = row_rsrc(hd, rbh, rowd), wg = row_rsrc(gd, rbg, rowd),
-               wp = row_rsrc(pvd, rbp, rowd);
+    const Rsrc wh = row_rsrc(hd, plh, zp), wg = row_rsrc(gd, plg, zp),
+               wp = row_rsrc(pvd, plp, zp);
 #pragma unroll
     for (int k = 1; k < 15; ++k) {
       const Real cx = Real(ex3(k)), cy = Real(ey3(k)), cz = Real(ez3(k));
@@ -362,7 +391,7 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
           w * (Real(3) * p + rho * (Real(3) * cu + Real(4.5) * cu * cu - Real(1.5) * usq));
       const Real G = w * (gbase + Real(3) * cF +
                           Real(4.5) * cu * (Real(2) * cF + Real(2) / Real(3) * cr + theta * cJ));
-      bst<Real>(wg, xcu, (uint32_t)(k - 1) * pb, g[k] - itau * (g[k] - geq) + srcg * G);
+      bst<Real>(wg, xcu, ybg[1] + (uint32_t)(k - 1) * pb, g[k] - itau * (g[k] - geq) + srcg * G);
     }
 #pragma unroll
     for (int i = 0; i < M; ++i) {
@@ -388,7 +417,7 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
         const Real R = sr * w * Real(3) * (cx * dd[0] + cy * dd[1] + cz * dd[2]);     // eq:N26
         const Real hn = P.h[i][k] - it * (P.h[i][k] - heq) + R;
         hsum += hn;
-        bst<Real>(wh, xcu, (uint32_t)(i * 15 + k) * pb, hn);
+        bst<Real>(wh, xcu, ybh[1] + (uint32_t)(i * 15 + k) * pb, hn);
       }
       // phi_i = pp + lo exactly; fl(phi_i) is stored as the new previous
       // phi and the k = 0 slot keeps (pp + lo - fl(phi_i)) - sum h_k
@@ -397,11 +426,11 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
       for (int k = 1; k < 15; ++k) lo += P.h[i][k];
       const Real bb = phi[i] - pp;
       const Real err = (pp - (phi[i] - bb)) + (lo - bb);
-      bst<Real>(wh, xcu, (uint32_t)(i * 15) * pb, err - hsum);
-      bst<Real>(wp, xcu, (uint32_t)i * pb, phi[i]);
+      bst<Real>(wh, xcu, ybh[1] + (uint32_t)(i * 15) * pb, err - hsum);
+      bst<Real>(wp, xcu, ybp + (uint32_t)i * pb, phi[i]);
     }
 #pragma unroll
-    for (int d = 0; d < 3; ++d) bst<Real>(wp, xcu, (uint32_t)(M + d) * pb, u[d]);
+    for (int d = 0; d < 3; ++d) bst<Real>(wp, xcu, ybp + (uint32_t)(M + d) * pb, u[d]);
   };
 
   // March: iteration j pulls plane mA = j - 2, computes C of mA - 1 and
@@ -411,6 +440,8 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
   // there they are issued at the collision.
   constexpr bool kEarly = !(sizeof(Real) == 8 && N >= 4);
   const int J = H + 4;
+  Real fv[M], fh[M];
+  load_phi(-2, fv, fh);
   for (int j = 0; j < J; ++j) {  // j is uniform over the block
     const int mA = j - 2;
     const int mC = mA - 2;
@@ -418,7 +449,8 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
     Col3<M, Real> col;
     if constexpr (kEarly)
       if (collide) pull_col(mC, col);
-    stageA(mA);
+    stageA(mA, fv, fh);
+    load_phi(mA + 1, fv, fh);
     __syncthreads();
     stageB(mA - 1);
     __syncthreads();
@@ -426,9 +458,72 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
   }
 }
 
+// The phi pass: phi_i = phi_prev + (d + sum_{k>=1} h_k) (eq:N28, the
+// pulled populations and the stored deviation of h_0) of every node of the
+// domain into the phi array.  One 64-lane wave per row segment of 64 nodes,
+// four rows per workgroup; no halo, so every population is read once.
+template <int N, typename Real>
+__global__ void __launch_bounds__(256) k_phi3(StepArgs a) {
+  constexpr int M = N - 1;
+  const NPL_CONST DomDesc *D = (const NPL_CONST DomDesc *)a.doms;
+  if (a.substep >= D->steps_left) return;
+  const int par = (a.substep + D->parity0) & 1;
+  const void *hs = D->h[par], *pvs = D->prev[par];
+  const int nx = D->nx, ny = D->ny, nz = D->nz;
+  const bool wall = D->wall != 0;
+  constexpr uint32_t SZ = sizeof(Real);
+  const uint32_t pb = (uint32_t)D->ps[0] * SZ;
+  const uint32_t rbh = (uint32_t)D->rs[0] * SZ, rbp = (uint32_t)D->rs[2] * SZ,
+                 rbf = (uint32_t)D->rsf * SZ;
+  const int lane = threadIdx.x & (k3W - 1);
+  const int y = blockIdx.y * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / k3W);  // uniform
+  const int z = blockIdx.z;
+  const int x = blockIdx.x * k3W + lane;
+  if (y >= ny || x >= nx) return;
+  const uint32_t xcu = (uint32_t)x * SZ;
+  const uint32_t xw = (uint32_t)(x == 0 ? nx - 1 : x - 1) * SZ;
+  const uint32_t xe = (uint32_t)(x == nx - 1 ? 0 : x + 1) * SZ;
+  const int yS = y == 0 ? ny - 1 : y - 1, yN = y == ny - 1 ? 0 : y + 1;
+  const uint32_t yb[3] = {(uint32_t)yS * rbh, (uint32_t)y * rbh, (uint32_t)yN * rbh};
+  const uint32_t plh = (uint32_t)ny * rbh;
+  const bool bS = wall && z == 0, bN = wall && z == nz - 1;
+  const Rsrc r0 = row_rsrc(hs, plh, z == 0 ? nz - 1 : z - 1);
+  const Rsrc r1 = row_rsrc(hs, plh, z);
+  const Rsrc r2 = row_rsrc(hs, plh, z == nz - 1 ? 0 : z + 1);
+  const Rsrc rp = row_rsrc(pvs, (uint32_t)ny * rbp, z);
+  Real f[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    Real lo = Real(0);
+#pragma unroll
+    for (int k = 0; k < 15; ++k) {
+      const int cx = ex3(k), cy = ey3(k), cz = ez3(k);
+      const bool b = (cz == 1 && bS) || (cz == -1 && bN);
+      const Rsrc r = b ? r1 : (cz == 1 ? r0 : (cz == -1 ? r2 : r1));
+      const uint32_t col = b ? xcu : (cx == 1 ? xw : (cx == -1 ? xe : xcu));
+      const uint32_t so = b ? yb[1] + (uint32_t)(i * 15 + opp3(k)) * pb
+                            : yb[1 - cy] + (uint32_t)(i * 15 + k) * pb;
+      lo += bld<Real>(r, col, so);
+    }
+    f[i] = bld<Real>(rp, xcu, (uint32_t)y * rbp + (uint32_t)i * pb) + lo;
+  }
+  const Rsrc wf = row_rsrc(D->phi3, (uint32_t)ny * rbf, z);
+#pragma unroll
+  for (int i = 0; i < M; ++i) bst<Real>(wf, xcu, (uint32_t)y * rbf + (uint32_t)i * pb, f[i]);
+}
+
 template <int N, int TY>
 constexpr int lds3_bytes(int bytes) {
-  return (k3PR + k3CR) * (N - 1) * TY * k3W * bytes;
+  return (k3PR + k3CR) * (N - 1) * TY * k3L * bytes;
+}
+
+template <int N>
+hipError_t launch_phi3(int precision, const StepArgs &a, dim3 grid, hipStream_t st) {
+  if (precision == 64)
+    hipLaunchKernelGGL((k_phi3<N, double>), grid, dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_phi3<N, float>), grid, dim3(256), 0, st, a);
+  return hipGetLastError();
 }
 
 template <int N, int TY>
@@ -463,19 +558,33 @@ int occ3(int precision) {
 
 }  // namespace
 
-// Rows of the tile: 16 (1024 threads, at most 128 registers each) where
-// that compiles without spills -- FP32 with N <= 3 -- else 8.
+// Rows of the tile: 8 (512 threads).  16 rows (1024 threads, at most 128
+// registers each) cover more interior per halo row but measured slower on
+// 256^3 (N = 3 FP32: 34% against 39% of the HBM roofline); NPLBM_TY3=16
+// selects it.
 int step3_ty(int N, int precision) {
+  (void)N;
+  (void)precision;
   if (const char *e = std::getenv("NPLBM_TY3")) {
     const int t = std::atoi(e);
     if (t == 8 || t == 16) return t;
   }
-  return (precision == 32 && N <= 3) ? 16 : 8;
+  return 8;
 }
 
-hipError_t launch_step3(int N, int precision, int ty, const StepArgs &a, int nblocks,
-                        hipStream_t st) {
+hipError_t launch_step3(int N, int precision, int ty, const StepArgs &a, int nblocks, int nx,
+                        int ny, int nz, hipStream_t st) {
   if (nblocks <= 0) return hipSuccess;
+  const dim3 pg((unsigned)((nx + k3W - 1) / k3W), (unsigned)((ny + 3) / 4), (unsigned)nz);
+  hipError_t e;
+  switch (N) {
+    case 2: e = launch_phi3<2>(precision, a, pg, st); break;
+    case 3: e = launch_phi3<3>(precision, a, pg, st); break;
+    case 4: e = launch_phi3<4>(precision, a, pg, st); break;
+    case 5: e = launch_phi3<5>(precision, a, pg, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
   if (ty == 16) {
     switch (N) {
       case 2: return launch3<2, 16>(precision, a, nblocks, st);
