@@ -381,8 +381,12 @@ Layout plan_layout(const nplbm_params *p) {
   const int N = p->N, M = N - 1;
   const size_t s = p->precision == 64 ? 8 : 4;
   L.pitch = (p->nx + 31) & ~31;  // rows start on 128-byte lines
-  if (const char *e = std::getenv("NPLBM_PITCH_PAD")) L.pitch += std::max(0, std::atoi(e)) & ~31;
   const bool d3 = is3d(p);
+  // 3-D: one extra cache line per plane row when the pitch is a multiple of
+  // 256 elements (256^3 N = 3 FP32: 40.5% against 38.8% of the HBM roofline;
+  // 2-D measured no difference)
+  if (d3 && L.pitch % 256 == 0) L.pitch += 32;
+  if (const char *e = std::getenv("NPLBM_PITCH_PAD")) L.pitch += std::max(0, std::atoi(e)) & ~31;
   const int nrows = p->ny * dom_nz(p);  // (z, y) lines of nodes
   const size_t n = (size_t)p->nx * nrows;
   // planes per group: CH populations, NS populations k >= 1, previous phi and u

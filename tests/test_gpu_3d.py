@@ -47,6 +47,14 @@ def test_3d_tiny_parity(n, wall):
     assert max(_parity(w, 25)) < TOL
 
 
+@pytest.mark.parametrize("N", [2, 3])
+def test_3d_sixteen_row_tiles_parity(N, monkeypatch):
+    # the 16-row tile variant (NPLBM_TY3=16, read when the domain is created)
+    monkeypatch.setenv("NPLBM_TY3", "16")
+    w = W.random_smooth3d(N, 100, 30, 12, seed=560 + N, wall_z=True, accept=oracle_accepts)
+    assert max(_parity(w, 20)) < TOL
+
+
 def test_3d_graph_path_and_variable_tau():
     # >= 64 steps (graph replay), unequal mu / rho, body force in all axes
     w = W.random_smooth3d(3, 48, 36, 24, seed=531, wall_z=True, accept=oracle_accepts)
