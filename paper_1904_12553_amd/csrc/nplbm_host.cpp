@@ -527,7 +527,7 @@ void xcd_order(std::vector<StripDesc> &s) {
 
 // Tile decomposition of a 3-D domain for the marching 3-D step kernel:
 // tiles of 64 columns starting on multiples of 64 (the last one ragged) and
-// at most ty - 4 rows, rows split as equally as possible, each marching
+// at most ty rows, rows split as equally as possible, each marching
 // through nz / nsz planes, nsz chosen so that the launch has about `target`
 // workgroups; neighbouring z segments march in opposite directions.
 void build_tiles3(int nx, int ny, int nz, int dom, int ty, int target,
@@ -540,7 +540,7 @@ void build_tiles3(int nx, int ny, int nz, int dom, int ty, int target,
   std::vector<int> xs, ys;
   for (int x = 0; x < nx; x += 64) xs.push_back(x);
   xs.push_back(nx);
-  split(ny, ty - 4, ys);
+  split(ny, ty, ys);
   const int nxy = (int)((xs.size() - 1) * (ys.size() - 1));
   if (target <= 0) target = 1024;
   int nsz = std::max(1, target / std::max(1, nxy));

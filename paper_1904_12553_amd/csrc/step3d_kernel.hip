@@ -12,10 +12,11 @@
 // Two passes per step.  The phi pass (k_phi3) pulls the CH populations of
 // every node once -- streaming fused into the load, bounce-back at z walls
 // -- and writes phi_i to a dense array.  The step pass (k_step3) then owns
-// a tile of interior nodes [x0, x1) x [y0, y1) (at most 64 x (ty - 4), x0 a
+// a tile of interior nodes [x0, x1) x [y0, y1) (at most 64 x TY, x0 a
 // multiple of 64, so loads and stores are whole cache lines) and marches
-// through the planes [z0, z1) with one 64-lane wave per row of the tile plus
-// a 2-row halo, ty rows; four lanes bring in the 2-column halos.  Each iteration copies phi of plane mA
+// through the planes [z0, z1) with one 64-lane wave per interior row; four
+// lanes of each row bring in the 2-column x-halos and four waves the 2-row
+// y-halos, so every wave collides.  Each iteration copies phi of plane mA
 // from the array into a 5-plane LDS ring (all threads; the next plane's
 // values are loaded right after, so they are in flight during the rest of
 // the iteration); computes C of plane mA - 1 on the tile plus a ring of one
@@ -99,8 +100,11 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
   const uint32_t rbh = (uint32_t)D->rs[0] * SZ, rbg = (uint32_t)D->rs[1] * SZ,
                  rbp = (uint32_t)D->rs[2] * SZ;
 
-  __shared__ Real sphi[k3PR][M][TY][k3L];
-  __shared__ Real sC[k3CR][M][TY][k3L];
+  // rows of the rings: phi on the TY interior rows and 2 halo rows each
+  // side, C on the interior rows and 1 each side
+  constexpr int kPRows = TY + 4, kCRows = TY + 2;
+  __shared__ Real sphi[k3PR][M][kPRows][k3L];
+  __shared__ Real sC[k3CR][M][kCRows][k3L];
 
   const int lane = threadIdx.x & (k3W - 1);
   const int ty = __builtin_amdgcn_readfirstlane(threadIdx.x / k3W);  // uniform
@@ -116,11 +120,20 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
   const uint32_t xcu = (uint32_t)xc * SZ;
   const uint32_t xw = (uint32_t)(xc == 0 ? nx - 1 : xc - 1) * SZ;  // x - 1
   const uint32_t xe = (uint32_t)(xc == nx - 1 ? 0 : xc + 1) * SZ;  // x + 1
-  const int yc = wrap_i(y0 - 2 + ty, ny);                            // uniform
+  // Rows: wave w owns interior row y0 + w (phi ring row w + 2, C ring row
+  // w + 1); waves 0..3 also bring the halo rows y0 - 2, y0 - 1, y0 + TY,
+  // y0 + TY + 1 (phi ring rows 0, 1, TY + 2, TY + 3), and waves 0, 1
+  // compute C of rows y0 - 1 and y0 + TY.  In a ragged tile (nyi < TY) the
+  // waves past the interior hold the halo rows below it, as the lanes past
+  // a ragged x end do.
+  const int yc = wrap_i(y0 + ty, ny);                                // uniform
   const int yS = yc == 0 ? ny - 1 : yc - 1, yN = yc == ny - 1 ? 0 : yc + 1;
+  const int pr = ty + 2, cr = ty + 1;                                // ring rows
   const bool lane_int = lane < nxi;
-  const bool row_int = ty >= 2 && ty < 2 + nyi;                      // uniform
-  const bool row_r1 = ty >= 1 && ty < 3 + nyi;                       // uniform
+  const bool row_int = ty < nyi;                                     // uniform
+  const bool hrow = ty < 4;                                          // uniform
+  const int yh = wrap_i(ty < 2 ? y0 - 2 + ty : y0 + TY - 2 + ty, ny);
+  const int prh = ty < 2 ? ty : TY + ty;                             // its ring row
   const int H = z1 - z0;
 
   auto plane_of = [&](int m) { return dir > 0 ? z0 + m : z1 - 1 - m; };
@@ -219,23 +232,41 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
   // all threads; the values of plane mA + 1 are loaded right after, so they
   // are in flight during the rest of the iteration
   const uint32_t rbf = (uint32_t)D->rsf * SZ, plf = (uint32_t)ny * rbf;
-  const uint32_t ybf = (uint32_t)yc * rbf;
+  const uint32_t ybf = (uint32_t)yc * rbf, ybfh = (uint32_t)yh * rbf;
   const void *phi3 = D->phi3;
-  auto load_phi = [&](int mA, Real (&f)[M], Real (&fh)[M]) {
+  // the values of the own row (f: column, fh: x-halo column of lanes < 4)
+  // and of the halo row of waves 0..3 (g, gh)
+  struct PhiRow {
+    Real f[M], fh[M], g[M], gh[M];
+  };
+  auto load_phi = [&](int mA, PhiRow &F) {
     const Rsrc r = row_rsrc(phi3, plf, phys_plane(plane_of(mA)));
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-      f[i] = bld<Real>(r, xcu, ybf + (uint32_t)i * pb);
-      fh[i] = bld<Real>(r, xh, ybf + (uint32_t)i * pb);
+      F.f[i] = bld<Real>(r, xcu, ybf + (uint32_t)i * pb);
+      F.fh[i] = bld<Real>(r, xh, ybf + (uint32_t)i * pb);
     }
+    if (hrow)
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        F.g[i] = bld<Real>(r, xcu, ybfh + (uint32_t)i * pb);
+        F.gh[i] = bld<Real>(r, xh, ybfh + (uint32_t)i * pb);
+      }
   };
-  auto stageA = [&](int mA, const Real (&f)[M], const Real (&fh)[M]) {
+  auto stageA = [&](int mA, const PhiRow &F) {
     const int slot = ring5(mA);
 #pragma unroll
-    for (int i = 0; i < M; ++i) sphi[slot][i][ty][col] = f[i];
+    for (int i = 0; i < M; ++i) sphi[slot][i][pr][col] = F.f[i];
     if (lane < 4)
 #pragma unroll
-      for (int i = 0; i < M; ++i) sphi[slot][i][ty][hcol] = fh[i];
+      for (int i = 0; i < M; ++i) sphi[slot][i][pr][hcol] = F.fh[i];
+    if (hrow) {
+#pragma unroll
+      for (int i = 0; i < M; ++i) sphi[slot][i][prh][col] = F.g[i];
+      if (lane < 4)
+#pragma unroll
+        for (int i = 0; i < M; ++i) sphi[slot][i][prh][hcol] = F.gh[i];
+    }
   };
 
   // ---- stage B: chemical potentials of march index mB -> LDS ----
@@ -243,7 +274,8 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
   // lane + 1 and, for the last two, 65 + lane.  Planes beyond a wall are
   // skipped: the collision next to the wall reads its own plane for the
   // mirror ghost.
-  auto chem_at = [&](int c, int s0, int sU, int sD, int sc) {
+  auto chem_at = [&](int q, int c, int s0, int sU, int sD, int sc) {
+    const int ty = q + 1;  // phi ring row of C ring row q
     Real phi[M], lap[M];
 #pragma unroll
     for (int i = 0; i < M; ++i) {
@@ -274,24 +306,30 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
       for (int j = 0; j < M; ++j) Ci -= K.lam[i][j] * lap[j];
 #pragma unroll
       for (int k = 0; k < N; ++k) Ci += K.KH[k][i] * wv[k];
-      sC[sc][i][ty][c] = Ci;
+      sC[sc][i][q][c] = Ci;
     }
   };
+  // the C ring rows of a wave: its own (row y0 + w) while w <= nyi, and for
+  // waves 0 / 1 rows y0 - 1 / y0 + TY
+  auto chem_row = [&](int q, int s0, int sU, int sD, int sc) {
+    if (lane + 1 <= nxi + 2) chem_at(q, lane + 1, s0, sU, sD, sc);
+    if (lane < 2 && 65 + lane <= nxi + 2) chem_at(q, 65 + lane, s0, sU, sD, sc);
+  };
   auto stageB = [&](int mB) {
-    if (!row_r1) return;
     if (wall) {
       const int z = plane_of(mB);
       if (z < 0 || z >= nz) return;
     }
     const int s0 = ring5(mB), sU = ring5(mB + dir), sD = ring5(mB - dir), sc = ring4(mB);
-    if (lane + 1 <= nxi + 2) chem_at(lane + 1, s0, sU, sD, sc);
-    if (lane < 2 && 65 + lane <= nxi + 2) chem_at(65 + lane, s0, sU, sD, sc);
+    if (ty <= nyi) chem_row(cr, s0, sU, sD, sc);
+    if (ty == 0) chem_row(0, s0, sU, sD, sc);
+    if (ty == 1 && nyi == TY) chem_row(TY + 1, s0, sU, sD, sc);
   };
 
   // eq:N31a on D3Q15 from an LDS ring: planes s0 (own), sU (z + 1), sD (z - 1)
   // around LDS column `lane` (2 .. 65)
-  auto grad3 = [&](const Real (*f)[M][TY][k3L], int lane, int s0, int sU, int sD, int i,
-                   Real &gx, Real &gy, Real &gz) {
+  auto grad3 = [&](auto f, int ty, int lane, int s0, int sU, int sD, int i, Real &gx, Real &gy,
+                   Real &gz) {
     const Real upp = f[sU][i][ty + 1][lane + 1], upm = f[sU][i][ty + 1][lane - 1];
     const Real ump = f[sU][i][ty - 1][lane + 1], umm = f[sU][i][ty - 1][lane - 1];
     const Real dpp = f[sD][i][ty + 1][lane + 1], dpm = f[sD][i][ty + 1][lane - 1];
@@ -325,11 +363,11 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
          J[3] = {Real(0), Real(0), Real(0)};
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-      phi[i] = sphi[s0][i][ty][ln];
-      Cv[i] = sC[c0][i][ty][ln];
+      phi[i] = sphi[s0][i][pr][ln];
+      Cv[i] = sC[c0][i][cr][ln];
       Real gp[3], gc[3];
-      grad3(sphi, ln, s0, sU, sD, i, gp[0], gp[1], gp[2]);
-      grad3(sC, ln, c0, cU, cD, i, gc[0], gc[1], gc[2]);
+      grad3(sphi, pr, ln, s0, sU, sD, i, gp[0], gp[1], gp[2]);
+      grad3(sC, cr, ln, c0, cU, cD, i, gc[0], gc[1], gc[2]);
       rho += K.rA[i] * phi[i];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
@@ -440,8 +478,8 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
   // there they are issued at the collision.
   constexpr bool kEarly = !(sizeof(Real) == 8 && N >= 4);
   const int J = H + 4;
-  Real fv[M], fh[M];
-  load_phi(-2, fv, fh);
+  PhiRow fr;
+  load_phi(-2, fr);
   for (int j = 0; j < J; ++j) {  // j is uniform over the block
     const int mA = j - 2;
     const int mC = mA - 2;
@@ -449,8 +487,8 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
     Col3<M, Real> col;
     if constexpr (kEarly)
       if (collide) pull_col(mC, col);
-    stageA(mA, fv, fh);
-    load_phi(mA + 1, fv, fh);
+    stageA(mA, fr);
+    load_phi(mA + 1, fr);
     __syncthreads();
     stageB(mA - 1);
     __syncthreads();
@@ -514,7 +552,7 @@ __global__ void __launch_bounds__(256) k_phi3(StepArgs a) {
 
 template <int N, int TY>
 constexpr int lds3_bytes(int bytes) {
-  return (k3PR + k3CR) * (N - 1) * TY * k3L * bytes;
+  return (k3PR * (TY + 4) + k3CR * (TY + 2)) * (N - 1) * k3L * bytes;
 }
 
 template <int N>
@@ -558,18 +596,18 @@ int occ3(int precision) {
 
 }  // namespace
 
-// Rows of the tile: 8 (512 threads).  16 rows (1024 threads, at most 128
-// registers each) cover more interior per halo row but measured slower on
-// 256^3 (N = 3 FP32: 34% against 39% of the HBM roofline); NPLBM_TY3=16
-// selects it.
+// Interior rows of a tile = waves of a workgroup: 8 for N <= 3, 4 for
+// N >= 4 (there FP64 rings of 8 rows would not fit in LDS, and in FP32 two
+// 4-row workgroups per CU measured faster than one of 8: 38% against 36% of
+// the HBM roofline on the N = 5 256^3 workload).  NPLBM_TY3 = 4 or 8
+// overrides.
 int step3_ty(int N, int precision) {
-  (void)N;
   (void)precision;
   if (const char *e = std::getenv("NPLBM_TY3")) {
     const int t = std::atoi(e);
-    if (t == 8 || t == 16) return t;
+    if (t == 4 || t == 8) return t;
   }
-  return 8;
+  return N >= 4 ? 4 : 8;
 }
 
 hipError_t launch_step3(int N, int precision, int ty, const StepArgs &a, int nblocks, int nx,
@@ -585,12 +623,12 @@ hipError_t launch_step3(int N, int precision, int ty, const StepArgs &a, int nbl
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
-  if (ty == 16) {
+  if (ty == 4) {
     switch (N) {
-      case 2: return launch3<2, 16>(precision, a, nblocks, st);
-      case 3: return launch3<3, 16>(precision, a, nblocks, st);
-      case 4: return launch3<4, 16>(precision, a, nblocks, st);
-      case 5: return launch3<5, 16>(precision, a, nblocks, st);
+      case 2: return launch3<2, 4>(precision, a, nblocks, st);
+      case 3: return launch3<3, 4>(precision, a, nblocks, st);
+      case 4: return launch3<4, 4>(precision, a, nblocks, st);
+      case 5: return launch3<5, 4>(precision, a, nblocks, st);
       default: return hipErrorInvalidValue;
     }
   }
@@ -604,12 +642,12 @@ hipError_t launch_step3(int N, int precision, int ty, const StepArgs &a, int nbl
 }
 
 int step3_blocks_per_cu(int N, int precision, int ty) {
-  if (ty == 16) {
+  if (ty == 4) {
     switch (N) {
-      case 2: return occ3<2, 16>(precision);
-      case 3: return occ3<3, 16>(precision);
-      case 4: return occ3<4, 16>(precision);
-      case 5: return occ3<5, 16>(precision);
+      case 2: return occ3<2, 4>(precision);
+      case 3: return occ3<3, 4>(precision);
+      case 4: return occ3<4, 4>(precision);
+      case 5: return occ3<5, 4>(precision);
       default: return 0;
     }
   }

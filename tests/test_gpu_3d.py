@@ -47,12 +47,13 @@ def test_3d_tiny_parity(n, wall):
     assert max(_parity(w, 25)) < TOL
 
 
-@pytest.mark.parametrize("N", [2, 3])
-def test_3d_sixteen_row_tiles_parity(N, monkeypatch):
-    # the 16-row tile variant (NPLBM_TY3=16, read when the domain is created)
-    monkeypatch.setenv("NPLBM_TY3", "16")
+@pytest.mark.parametrize("N,ty", [(2, "4"), (3, "4"), (4, "8"), (5, "8")])
+def test_3d_other_tile_height_parity(N, ty, monkeypatch):
+    # the tile height the default does not pick for this N (NPLBM_TY3, read
+    # when the domain is created): 4 rows for N <= 3, 8 rows for N >= 4
+    monkeypatch.setenv("NPLBM_TY3", ty)
     w = W.random_smooth3d(N, 100, 30, 12, seed=560 + N, wall_z=True, accept=oracle_accepts)
-    assert max(_parity(w, 20)) < TOL
+    assert max(_parity(w, 20)) < TOL, ty
 
 
 def test_3d_graph_path_and_variable_tau():
