@@ -602,10 +602,11 @@ int occ3(int precision) {
 // the HBM roofline on the N = 5 256^3 workload).  NPLBM_TY3 = 4 or 8
 // overrides.
 int step3_ty(int N, int precision) {
-  (void)precision;
   if (const char *e = std::getenv("NPLBM_TY3")) {
     const int t = std::atoi(e);
-    if (t == 4 || t == 8) return t;
+    const int bytes = precision == 64 ? 8 : 4;
+    const int lds = (k3PR * (t + 4) + k3CR * (t + 2)) * (N - 1) * k3L * bytes;
+    if (t == 4 || (t == 8 && lds <= 160 * 1024)) return t;
   }
   return N >= 4 ? 4 : 8;
 }

@@ -47,13 +47,26 @@ def test_3d_tiny_parity(n, wall):
     assert max(_parity(w, 25)) < TOL
 
 
-@pytest.mark.parametrize("N,ty", [(2, "4"), (3, "4"), (4, "8"), (5, "8")])
-def test_3d_other_tile_height_parity(N, ty, monkeypatch):
+@pytest.mark.parametrize("N,ty,prec", [(2, "4", 64), (3, "4", 64), (4, "8", 64), (5, "8", 32)])
+def test_3d_other_tile_height(N, ty, prec, monkeypatch):
     # the tile height the default does not pick for this N (NPLBM_TY3, read
-    # when the domain is created): 4 rows for N <= 3, 8 rows for N >= 4
-    monkeypatch.setenv("NPLBM_TY3", ty)
+    # when the domain is created): 4 rows for N <= 3, 8 rows for N >= 4;
+    # FP64 against the oracle, FP32 (N = 5: 8-row FP64 rings do not fit in
+    # LDS) against the default FP64 kernel
     w = W.random_smooth3d(N, 100, 30, 12, seed=560 + N, wall_z=True, accept=oracle_accepts)
-    assert max(_parity(w, 20)) < TOL, ty
+    if prec == 64:
+        monkeypatch.setenv("NPLBM_TY3", ty)
+        assert max(_parity(w, 20)) < TOL, ty
+    else:
+        ref = gpu_domain(w, precision=64)
+        ref.step(20)
+        c64 = ref.macro()[0]
+        ref.close()
+        monkeypatch.setenv("NPLBM_TY3", ty)
+        d = gpu_domain(w, precision=32)
+        d.step(20)
+        assert maxabs(d.macro()[0], c64) < 1e-5
+        d.close()
 
 
 def test_3d_graph_path_and_variable_tau():
