@@ -189,6 +189,14 @@ int nplbm_diagnostics(nplbm_domain *d, double *mass_out, double *max_sum_dev,
 int nplbm_laplace(nplbm_domain *d, double xc, double yc, double r_in,
                   double r_out, double *dp);
 
+/*
+ * The same for a 3-D domain and a spherical droplet centred at
+ * (xc, yc, zc) (Sec. 4.1's test with the jump 2 sigma / R of a sphere).
+ * NPLBM_EINVAL on a 2-D domain.  Synchronous.
+ */
+int nplbm_laplace3(nplbm_domain *d, double xc, double yc, double zc, double r_in,
+                   double r_out, double *dp);
+
 /* Number of steps taken since nplbm_set_fields, or -1 for NULL. */
 int64_t nplbm_time(const nplbm_domain *d);
 

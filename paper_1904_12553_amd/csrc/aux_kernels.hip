@@ -369,15 +369,16 @@ __global__ void k_diag_final(const double *partials, int nq, int nblk, const int
 }
 
 // Laplace: sums and counts of p inside r <= r_in and outside r >= r_out
-__global__ void k_laplace_partial(const double *p, int nx, int ny, double xc, double yc,
-                                  double r_in, double r_out, double *partials) {
+__global__ void k_laplace_partial(const double *p, int nx, int ny, int nz, double xc, double yc,
+                                  double zc, double r_in, double r_out, double *partials) {
   __shared__ double red[kThreads / 64][4];
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  const int64_t n = (int64_t)nx * ny;
+  const int64_t n = (int64_t)nx * ny * nz;
   for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < n;
        id += (int64_t)gridDim.x * blockDim.x) {
-    const double x = (double)(id % nx), y = (double)(id / nx);
-    const double r = sqrt((x - xc) * (x - xc) + (y - yc) * (y - yc));
+    const double x = (double)(id % nx), y = (double)((id / nx) % ny),
+                 z = (double)(id / ((int64_t)nx * ny));
+    const double r = sqrt((x - xc) * (x - xc) + (y - yc) * (y - yc) + (z - zc) * (z - zc));
     if (r <= r_in) {
       acc[0] += p[id];
       acc[1] += 1.0;
@@ -503,10 +504,11 @@ hipError_t launch_diag(const double *c, int N, int64_t n, double *partials, int 
   return hipGetLastError();
 }
 
-hipError_t launch_laplace(const double *p, int nx, int ny, double xc, double yc, double r_in,
-                          double r_out, double *partials, int nblk, double *out, hipStream_t st) {
-  hipLaunchKernelGGL(k_laplace_partial, dim3(nblk), dim3(kThreads), 0, st, p, nx, ny, xc, yc,
-                     r_in, r_out, partials);
+hipError_t launch_laplace(const double *p, int nx, int ny, int nz, double xc, double yc,
+                          double zc, double r_in, double r_out, double *partials, int nblk,
+                          double *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_laplace_partial, dim3(nblk), dim3(kThreads), 0, st, p, nx, ny, nz, xc, yc,
+                     zc, r_in, r_out, partials);
   hipLaunchKernelGGL(k_laplace_final, dim3(1), dim3(64), 0, st, partials, nblk, out);
   return hipGetLastError();
 }

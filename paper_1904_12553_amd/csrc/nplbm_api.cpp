@@ -388,11 +388,27 @@ int nplbm_laplace(nplbm_domain *d, double xc, double yc, double r_in, double r_o
   if (!check_domain(d) || !dp) return fail(NPLBM_EINVAL, "NULL argument");
   if (!d->initialised) return fail(NPLBM_ESTATE, "nplbm_set_fields was not called");
   if (!(r_in >= 0.0) || !(r_out >= r_in)) return fail(NPLBM_EINVAL, "need 0 <= r_in <= r_out");
-  if (d->d3) return fail(NPLBM_EINVAL, "nplbm_laplace measures 2-D domains only");
+  if (d->d3) return fail(NPLBM_EINVAL, "nplbm_laplace measures 2-D domains (see nplbm_laplace3)");
   int rc = readback(d, true);
   if (rc) return rc;
-  hipError_t e = launch_laplace(dptr(d, d->L.p), d->p.nx, d->p.ny, xc, yc, r_in, r_out,
+  hipError_t e = launch_laplace(dptr(d, d->L.p), d->p.nx, d->p.ny, 1, xc, yc, 0.0, r_in, r_out,
                                 dptr(d, d->L.partials), d->L.nblk, dptr(d, d->L.out), d->stream);
+  if (e != hipSuccess) return hip_fail(e, "laplace launch");
+  return copy_out(d, dp, d->L.out, 8);
+}
+
+int nplbm_laplace3(nplbm_domain *d, double xc, double yc, double zc, double r_in, double r_out,
+                   double *dp) {
+  clear_error();
+  if (!check_domain(d) || !dp) return fail(NPLBM_EINVAL, "NULL argument");
+  if (!d->initialised) return fail(NPLBM_ESTATE, "nplbm_set_fields was not called");
+  if (!(r_in >= 0.0) || !(r_out >= r_in)) return fail(NPLBM_EINVAL, "need 0 <= r_in <= r_out");
+  if (!d->d3) return fail(NPLBM_EINVAL, "nplbm_laplace3 measures 3-D domains (see nplbm_laplace)");
+  int rc = readback(d, true);
+  if (rc) return rc;
+  hipError_t e = launch_laplace(dptr(d, d->L.p), d->p.nx, d->p.ny, d->p.nz, xc, yc, zc, r_in,
+                                r_out, dptr(d, d->L.partials), d->L.nblk, dptr(d, d->L.out),
+                                d->stream);
   if (e != hipSuccess) return hip_fail(e, "laplace launch");
   return copy_out(d, dp, d->L.out, 8);
 }

@@ -178,8 +178,11 @@ hipError_t launch_macro(const DomDesc *dd_dev, const DomDesc &dd, int precision,
 int diag_blocks(int64_t n);
 hipError_t launch_diag(const double *c, int N, int64_t n, double *partials, int nblk,
                        double *out, hipStream_t st);
-hipError_t launch_laplace(const double *p, int nx, int ny, double xc, double yc,
-                          double r_in, double r_out, double *partials, int nblk,
+// Laplace jump on a dense FP64 p field of nx * ny * nz nodes (nz = 1 in
+// 2-D): mean of p within distance r_in of (xc, yc, zc) minus the mean at
+// distance >= r_out.
+hipError_t launch_laplace(const double *p, int nx, int ny, int nz, double xc, double yc,
+                          double zc, double r_in, double r_out, double *partials, int nblk,
                           double *out, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, size_t nbytes, hipStream_t st);
 

@@ -29,7 +29,7 @@ ERRORS = {-1: "EINVAL", -2: "ENOTSPD", -3: "ENOMEM", -4: "EDEVICE", -5: "ETOOBIG
 EXPORTS = [
     "nplbm_last_error", "nplbm_validate", "nplbm_footprint", "nplbm_create",
     "nplbm_set_fields", "nplbm_step", "nplbm_get_c", "nplbm_get_u", "nplbm_get_p",
-    "nplbm_diagnostics", "nplbm_laplace", "nplbm_time", "nplbm_sync", "nplbm_destroy",
+    "nplbm_diagnostics", "nplbm_laplace", "nplbm_laplace3", "nplbm_time", "nplbm_sync", "nplbm_destroy",
     "nplbm_state_bytes", "nplbm_get_state", "nplbm_set_state", "nplbm_device_copy",
     "nplbm_server_create", "nplbm_submit", "nplbm_server_pump", "nplbm_poll",
     "nplbm_result", "nplbm_server_stats", "nplbm_server_destroy",
@@ -81,6 +81,7 @@ def lib():
             "nplbm_get_u": ([vp, dp], c_int),
             "nplbm_get_p": ([vp, dp], c_int),
             "nplbm_diagnostics": ([vp, dp, dp, ctypes.POINTER(c_i64)], c_int),
+            "nplbm_laplace3": ([vp] + [ctypes.c_double] * 5 + [dp], c_int),
             "nplbm_laplace": ([vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                ctypes.c_double, dp], c_int),
             "nplbm_time": ([vp], c_i64),
@@ -264,10 +265,15 @@ class Domain:
         _check(lib().nplbm_diagnostics(self._h, _dp(mass), ctypes.byref(dev), ctypes.byref(bad)))
         return mass, dev.value, bad.value
 
-    def laplace(self, xc, yc, r_in, r_out) -> float:
+    def laplace(self, xc, yc, r_in, r_out, zc=None) -> float:
+        """Laplace jump about (xc, yc) in 2-D, about (xc, yc, zc) in 3-D."""
         dp = ctypes.c_double()
-        _check(lib().nplbm_laplace(self._h, float(xc), float(yc), float(r_in), float(r_out),
-                                   ctypes.byref(dp)))
+        if self.dim == 3:
+            _check(lib().nplbm_laplace3(self._h, float(xc), float(yc), float(zc), float(r_in),
+                                        float(r_out), ctypes.byref(dp)))
+        else:
+            _check(lib().nplbm_laplace(self._h, float(xc), float(yc), float(r_in), float(r_out),
+                                       ctypes.byref(dp)))
         return dp.value
 
     def get_state(self):

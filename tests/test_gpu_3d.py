@@ -69,6 +69,22 @@ def test_3d_other_tile_height(N, ty, prec, monkeypatch):
         d.close()
 
 
+def test_3d_checkpoint_resume_is_bitwise():
+    w = W.random_smooth3d(4, 70, 20, 16, seed=570, wall_z=True, accept=oracle_accepts)
+    d1 = gpu_domain(w, precision=32)
+    d1.step(17)
+    st, t = d1.get_state()
+    d1.step(23)
+    d2 = gpu_domain(w, precision=32)
+    d2.set_state(st, t)
+    d2.step(23)
+    assert d2.time == d1.time == 40
+    for a, b in zip(d1.macro(), d2.macro()):
+        assert np.array_equal(a, b)
+    d1.close()
+    d2.close()
+
+
 def test_3d_graph_path_and_variable_tau():
     # >= 64 steps (graph replay), unequal mu / rho, body force in all axes
     w = W.random_smooth3d(3, 48, 36, 24, seed=531, wall_z=True, accept=oracle_accepts)
@@ -116,7 +132,12 @@ def test_3d_laplace_sphere():
         x, y, z = W.grid3(64, 64, 64)
         r = np.sqrt((x - 32) ** 2 + (y - 32) ** 2 + (z - 32) ** 2)
         R = (3 * c[1].sum() / (4 * np.pi)) ** (1 / 3)
-        dp = p[r < R - 8].mean() - p[r > R + 8].mean()
+        dp = p[r <= R - 8].mean() - p[r >= R + 8].mean()
+        # the same jump reduced on the GPU in FP64
+        d = gpu_domain(w, precision=prec)
+        d.step(3000)
+        assert d.laplace(32, 32, R - 8, R + 8, zc=32) == pytest.approx(dp, rel=1e-9, abs=1e-15)
+        d.close()
         res[prec] = dp * R / (2 * 1e-3)
         print(f"fp{prec}: R = {R:.3f}, dp R / 2 sigma = {res[prec]:.4f}, max|u| = {np.abs(u).max():.2e}")
     assert abs(res[64] - 1) < 0.03
