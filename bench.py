@@ -133,7 +133,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only: the domain and the serving "
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the domain and the serving "
                                    "loop live on a single MI355X; multi-GPU slab decomposition "
                                    "is a design note, not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
