@@ -2,8 +2,8 @@
 
 Tolerance: 1e-10 max-abs on c, u and p (the stated FP64 bar).  Inputs are
 seeded and synthetic (workloads module); sizes span several strips of the
-marching kernel (60 interior columns, 16+ rows) with ragged last strips in x
-and y, both boundary kinds, N = 2..5, spatially varying tau_g (unequal
+marching kernel (48 interior columns in FP64, 16+ rows) with ragged last
+strips in x and y, both boundary kinds, N = 2..5, spatially varying tau_g (unequal
 mu/rho), a body force, and the graph path (>= 64 steps).
 """
 import numpy as np

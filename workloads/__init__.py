@@ -324,10 +324,12 @@ def cosine_perturbation(n: int = 64, c0: float = 0.05, amp: float = 1e-4,
 
 def random_smooth(N: int, nx: int, ny: int, seed: int, wall_y: bool = False,
                   amp_u: float = 1e-2, accept=None, W: float = 4.0,
-                  unequal: bool = True) -> Workload:
+                  unequal: bool = True, sigma_range=(0.5e-3, 2e-3)) -> Workload:
     """Small random test case: N smooth random non-negative fractions that sum
-    to one, a smooth random velocity, random tensions, densities in [1, 3]
-    and per-phase viscosities (so tau_g varies in space)."""
+    to one, a smooth random velocity, random tensions (uniform over
+    ``sigma_range``; large N needs a narrow range for an SPD mixing matrix),
+    densities in [1, 3] and per-phase viscosities (so tau_g varies in
+    space)."""
     rng = np.random.default_rng(seed)
     x, y = grid(nx, ny)
     fields = []
@@ -347,7 +349,7 @@ def random_smooth(N: int, nx: int, ny: int, seed: int, wall_y: bool = False,
         ph = rng.uniform(0, 2 * np.pi)
         u[d] = amp_u * np.sin(2 * np.pi * (kx * x / nx + ky * y / ny) + ph)
     rho = rng.uniform(1.0, 3.0, size=N) if unequal else np.ones(N)
-    sigma, _ = draw_sigma(N, seed + 1, accept=accept, rho=rho)
+    sigma, _ = draw_sigma(N, seed + 1, *sigma_range, accept=accept, rho=rho)
     mu = rng.uniform(0.05, 0.3, size=N) * rho
     return Workload(f"random_N{N}_{nx}x{ny}", N, nx, ny, sigma, rho, mu, c, u,
                     mobility=float(rng.uniform(0.05, 0.2)), tau_phi=float(rng.uniform(0.7, 1.2)),
