@@ -500,6 +500,13 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
 // pulled populations and the stored deviation of h_0) of every node of the
 // domain into the phi array.  One 64-lane wave per row segment of 64 nodes,
 // four rows per workgroup; no halo, so every population is read once.
+//
+// Blocks are numbered for the 8 XCDs: hardware block b runs on XCD b % 8,
+// and XCD x takes the x-th contiguous eighth of the (x, y, z)-ordered block
+// list, in order.  Blocks next to each other in x then run on one XCD at
+// about the same time, so the cache line that two of them pull from (the
+// one holding the column left or right of a 64-column segment) comes from
+// that XCD's L2 the second time.
 template <int N, typename Real>
 __global__ void __launch_bounds__(256) k_phi3(StepArgs a) {
   constexpr int M = N - 1;
@@ -513,10 +520,15 @@ __global__ void __launch_bounds__(256) k_phi3(StepArgs a) {
   const uint32_t pb = (uint32_t)D->ps[0] * SZ;
   const uint32_t rbh = (uint32_t)D->rs[0] * SZ, rbp = (uint32_t)D->rs[2] * SZ,
                  rbf = (uint32_t)D->rsf * SZ;
+  const int gx = (nx + k3W - 1) / k3W, gy = (ny + 3) / 4;
+  const int nblk = gx * gy * nz, per = (nblk + 7) / 8;
+  const int t = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (t >= nblk) return;
+  const int bx = t % gx, by = (t / gx) % gy;
   const int lane = threadIdx.x & (k3W - 1);
-  const int y = blockIdx.y * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / k3W);  // uniform
-  const int z = blockIdx.z;
-  const int x = blockIdx.x * k3W + lane;
+  const int y = by * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / k3W);  // uniform
+  const int z = t / (gx * gy);
+  const int x = bx * k3W + lane;
   if (y >= ny || x >= nx) return;
   const uint32_t xcu = (uint32_t)x * SZ;
   const uint32_t xw = (uint32_t)(x == 0 ? nx - 1 : x - 1) * SZ;
@@ -614,7 +626,11 @@ int step3_ty(int N, int precision) {
 hipError_t launch_step3(int N, int precision, int ty, const StepArgs &a, int nblocks, int nx,
                         int ny, int nz, hipStream_t st) {
   if (nblocks <= 0) return hipSuccess;
-  const dim3 pg((unsigned)((nx + k3W - 1) / k3W), (unsigned)((ny + 3) / 4), (unsigned)nz);
+  // one block per 64 x 4 row segments of a plane, in a 1-D grid whose
+  // size is a multiple of 8 (the phi pass maps block numbers to XCDs)
+  const int64_t nphi = (int64_t)((nx + k3W - 1) / k3W) * ((ny + 3) / 4) * nz;
+  if (nphi > (int64_t)1 << 30) return hipErrorInvalidValue;
+  const dim3 pg((unsigned)((nphi + 7) / 8 * 8));
   hipError_t e;
   switch (N) {
     case 2: e = launch_phi3<2>(precision, a, pg, st); break;
