@@ -99,7 +99,8 @@ void release(nplbm_server *s, Req *r) {
 int admit(nplbm_server *s, Req *r) {
   void *m = nullptr;
   hipError_t e = hipMalloc(&m, r->bytes);
-  if (e != hipSuccess) return fail(NPLBM_ENOMEM, "hipMalloc(%zu) failed", r->bytes);
+  if (e != hipSuccess)
+    return fail(NPLBM_ENOMEM, "hipMalloc(%zu): %s", r->bytes, hipGetErrorString(e));
   r->base = static_cast<unsigned char *>(m);
   s->used += r->bytes;
   int slot = -1;
@@ -283,7 +284,7 @@ int nplbm_server_create(size_t hbm_budget, int32_t max_slots, int32_t quantum, v
   hipError_t e = hipMalloc(&s->descs_dev, sizeof(DomDesc) * (size_t)max_slots);
   if (e != hipSuccess) {
     delete s;
-    return fail(NPLBM_ENOMEM, "descriptor table allocation failed");
+    return fail(NPLBM_ENOMEM, "descriptor table allocation: %s", hipGetErrorString(e));
   }
   *out = s;
   return NPLBM_OK;

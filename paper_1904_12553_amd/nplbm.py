@@ -66,6 +66,11 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_1904_12553_amd.build_lib`")
+        # torch first: its HIP runtime is then the one the library binds to
+        # (same soname), so streams and device memory handed over from torch
+        # belong to the library's runtime.  Loaded the other way round, the
+        # process holds two HIP runtimes and the library's may see no device.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         c_int, c_i32, c_i64, c_u64 = ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
         vp, dp, sz = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t

@@ -143,3 +143,21 @@ def test_footprint_counts_the_state_of_both_lattices():
         state2, state3 = 2 * 10 * N * 4 * nodes, 2 * (16 * N + 1) * 4 * nodes
         assert state2 < n2 < state2 * 1.05 + (4 * N + 6) * 8 * nodes
         assert state3 < n3 < state3 * 1.05 + (4 * N + 8) * 8 * nodes
+
+
+def test_library_shares_torchs_hip_runtime():
+    """Loading the library first must not bring a second HIP runtime into
+    the process: the binding imports torch before the library, so both use
+    one runtime (streams and device memory are handed between them).  Run in
+    a fresh interpreter, where nothing has loaded torch yet."""
+    import subprocess
+    import sys
+    code = ("from paper_1904_12553_amd import nplbm; nplbm.lib(); import torch; "
+            "maps = open('/proc/self/maps').read().splitlines(); "
+            "print(sorted({l.split()[-1] for l in maps if 'libamdhip64' in l}))")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                       timeout=300, env=dict(os.environ, PYTHONPATH=root))
+    assert r.returncode == 0, r.stderr
+    libs = eval(r.stdout.strip().splitlines()[-1])
+    assert len(libs) == 1, libs

@@ -67,3 +67,22 @@ def test_budget_admission_and_too_big():
     for _ in range(20):
         srv.pump()
     assert srv.poll(t1) == 2 and srv.poll(t2) == 2
+
+
+def test_server_in_a_fresh_process_that_loads_the_library_first():
+    # the library is loaded (by the tension check) before anything else
+    # touches the GPU; the server must still find the device
+    import os
+    import subprocess
+    import sys
+    code = ("import paper_1904_12553_amd as P, workloads as W; "
+            "w = W.static_droplet(64, 64, R=16); assert P.accepts(w.sigma, w.rho); "
+            "s = P.Server(hbm_budget=1 << 30, max_slots=2, quantum=8); "
+            "t = s.submit(w.c, w.u, nsteps=20, precision=32, **w.params()); "
+            "[s.pump() for _ in range(5)]; assert s.poll(t) == 2; s.result(t); s.close(); "
+            "print('server ok')")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    print("case fresh-process server", flush=True)
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                       timeout=200, env=dict(os.environ, PYTHONPATH=root))
+    assert r.returncode == 0 and "server ok" in r.stdout, r.stdout + r.stderr
