@@ -93,6 +93,11 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
   const void *gs = D->g[par], *gd = D->g[par ^ 1];
   const void *pvs = D->prev[par], *pvd = D->prev[par ^ 1];
   const NPL_CONST Consts<Real> &K = *consts3<Real>(D);
+  // the NS part of the collision in FP64 arithmetic in both modes (FP32
+  // populations stay FP32): FP32 rounding there biases each node's momentum
+  // in the same direction wherever the flow state repeats
+  using Acc = double;
+  const NPL_CONST Consts<double> &KD = *consts3<double>(D);
   const int nx = D->nx, ny = D->ny, nz = D->nz;
   const bool wall = D->wall != 0;
   constexpr uint32_t SZ = sizeof(Real);
@@ -359,8 +364,8 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
     // not store
     const int ln = col;
     Real phi[M], Cv[M];
-    Real rho = K.ra, gr[3] = {Real(0), Real(0), Real(0)}, F[3] = {Real(0), Real(0), Real(0)},
-         J[3] = {Real(0), Real(0), Real(0)};
+    Acc rho = KD.ra, gr[3] = {Acc(0), Acc(0), Acc(0)}, F[3] = {Acc(0), Acc(0), Acc(0)},
+         J[3] = {Acc(0), Acc(0), Acc(0)};
 #pragma unroll
     for (int i = 0; i < M; ++i) {
       phi[i] = sphi[s0][i][pr][ln];
@@ -368,67 +373,67 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
       Real gp[3], gc[3];
       grad3(sphi, pr, ln, s0, sU, sD, i, gp[0], gp[1], gp[2]);
       grad3(sC, cr, ln, c0, cU, cD, i, gc[0], gc[1], gc[2]);
-      rho += K.rA[i] * phi[i];
+      rho += KD.rA[i] * phi[i];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        gr[d] += K.rA[i] * gp[d];
+        gr[d] += KD.rA[i] * gp[d];
         F[d] += Cv[i] * gp[d];
-        J[d] += K.Jc[i] * gc[d];
+        J[d] += KD.Jc[i] * gc[d];
       }
     }
-    F[0] += rho * K.gx;
-    F[1] += rho * K.gy;
-    F[2] += rho * K.gz;
-    Real itau, srcg, theta;
-    if (K.const_tau) {
-      itau = K.itau_g;
-      srcg = K.src_g;
-      theta = K.theta_g;
+    F[0] += rho * KD.gx;
+    F[1] += rho * KD.gy;
+    F[2] += rho * KD.gz;
+    Acc itau, srcg, theta;
+    if (KD.const_tau) {
+      itau = KD.itau_g;
+      srcg = KD.src_g;
+      theta = KD.theta_g;
     } else {
-      Real mu = K.ma;
+      Acc mu = KD.ma;
 #pragma unroll
-      for (int i = 0; i < M; ++i) mu += K.mA[i] * phi[i];
-      const Real tm = Real(3) * mu / rho;  // tau_g - 1/2 (eq:N21_1)
-      itau = Real(1) / (Real(0.5) + tm);
-      srcg = Real(1) - Real(0.5) * itau;
-      theta = Real(1) / tm;
+      for (int i = 0; i < M; ++i) mu += KD.mA[i] * phi[i];
+      const Acc tm = Acc(3) * mu / rho;  // tau_g - 1/2 (eq:N21_1)
+      itau = Acc(1) / (Acc(0.5) + tm);
+      srcg = Acc(1) - Acc(0.5) * itau;
+      theta = Acc(1) / tm;
     }
-    const Real(&g)[15] = P.g;
-    Real m[3] = {Real(0), Real(0), Real(0)}, sumg = Real(0);
+    const Real(&g)[15] = P.g;  // every use below is promoted to Acc
+    Acc m[3] = {Acc(0), Acc(0), Acc(0)}, sumg = Acc(0);
 #pragma unroll
     for (int k = 1; k < 15; ++k) {
-      if (ex3(k)) m[0] += Real(ex3(k)) * g[k];
-      if (ey3(k)) m[1] += Real(ey3(k)) * g[k];
-      if (ez3(k)) m[2] += Real(ez3(k)) * g[k];
+      if (ex3(k)) m[0] += Acc(ex3(k)) * g[k];
+      if (ey3(k)) m[1] += Acc(ey3(k)) * g[k];
+      if (ez3(k)) m[2] += Acc(ez3(k)) * g[k];
       sumg += g[k];
     }
-    const Real irho = Real(1) / rho;
-    Real u[3];
+    const Acc irho = Acc(1) / rho;
+    Acc u[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) u[d] = (m[d] + Real(0.5) * F[d]) * irho;  // eq:N22_1
-    const Real usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    const Real udr = u[0] * gr[0] + u[1] * gr[1] + u[2] * gr[2];
+    for (int d = 0; d < 3; ++d) u[d] = (m[d] + Acc(0.5) * F[d]) * irho;  // eq:N22_1
+    const Acc usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const Acc udr = u[0] * gr[0] + u[1] * gr[1] + u[2] * gr[2];
     // eq:N23 with w_0 = 2/9: c_s^2 / (1 - w_0) = 3/7, rho s_0 = -(1/3) rho |u|^2
-    const Real p = Real(3) / Real(7) * (sumg + Real(0.5) * udr - Real(1) / Real(3) * rho * usq);
-    const Real uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
-    const Real Ju = J[0] * u[0] + J[1] * u[1] + J[2] * u[2];
+    const Acc p = Acc(3) / Acc(7) * (sumg + Acc(0.5) * udr - Acc(1) / Acc(3) * rho * usq);
+    const Acc uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+    const Acc Ju = J[0] * u[0] + J[1] * u[1] + J[2] * u[2];
     // isotropic part of eq:N20_1: u.grad(rho) - tr(T) / (2 c_s^2)
-    const Real gbase = udr - Real(1.5) * (Real(2) * uF + Real(2) / Real(3) * udr + theta * Ju);
+    const Acc gbase = udr - Acc(1.5) * (Acc(2) * uF + Acc(2) / Acc(3) * udr + theta * Ju);
     if (!lane_int) return;
     const Rsrc wh = row_rsrc(hd, plh, zp), wg = row_rsrc(gd, plg, zp),
                wp = row_rsrc(pvd, plp, zp);
 #pragma unroll
     for (int k = 1; k < 15; ++k) {
-      const Real cx = Real(ex3(k)), cy = Real(ey3(k)), cz = Real(ez3(k));
-      const Real w = w3<Real>(k);
-      const Real cu = cx * u[0] + cy * u[1] + cz * u[2];
-      const Real cF = cx * F[0] + cy * F[1] + cz * F[2];
-      const Real cr = cx * gr[0] + cy * gr[1] + cz * gr[2];
-      const Real cJ = cx * J[0] + cy * J[1] + cz * J[2];
-      const Real geq =
-          w * (Real(3) * p + rho * (Real(3) * cu + Real(4.5) * cu * cu - Real(1.5) * usq));
-      const Real G = w * (gbase + Real(3) * cF +
-                          Real(4.5) * cu * (Real(2) * cF + Real(2) / Real(3) * cr + theta * cJ));
+      const Acc cx = Acc(ex3(k)), cy = Acc(ey3(k)), cz = Acc(ez3(k));
+      const Acc w = w3<Acc>(k);
+      const Acc cu = cx * u[0] + cy * u[1] + cz * u[2];
+      const Acc cF = cx * F[0] + cy * F[1] + cz * F[2];
+      const Acc cr = cx * gr[0] + cy * gr[1] + cz * gr[2];
+      const Acc cJ = cx * J[0] + cy * J[1] + cz * J[2];
+      const Acc geq =
+          w * (Acc(3) * p + rho * (Acc(3) * cu + Acc(4.5) * cu * cu - Acc(1.5) * usq));
+      const Acc G = w * (gbase + Acc(3) * cF +
+                          Acc(4.5) * cu * (Acc(2) * cF + Acc(2) / Acc(3) * cr + theta * cJ));
       bst<Real>(wg, xcu, ybg[1] + (uint32_t)(k - 1) * pb, g[k] - itau * (g[k] - geq) + srcg * G);
     }
 #pragma unroll

@@ -148,6 +148,17 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   const void *gs = D->g[par], *gd = D->g[par ^ 1];
   const void *pvs = D->prev[par], *pvd = D->prev[par ^ 1];
   const NPL_CONST Consts<Real> &K = *consts_of<Real>(D);
+  // The NS part of the collision (density, forces, u, p, g^eq, G and the
+  // g update) is evaluated in FP64 arithmetic in both modes; the FP32 mode
+  // still stores FP32 populations.  Evaluated in FP32, the rounding of g^eq
+  // and of the update leaves each node's momentum off by a fraction of an
+  // ulp, in the same direction wherever the flow state repeats (inside a
+  // moving droplet), so droplets gain momentum steadily and interfaces drift
+  // as t^2: FP32 vs FP64 on the 512^2 N = 4 droplet collision went from
+  // 2.6e-5 to 7e-8 in c after 2000 steps (2e-3 to 7e-7 after 50000), for
+  // 2.7% more kernel time.
+  using Acc = double;
+  const NPL_CONST Consts<double> &KD = *consts_of<double>(D);
   const int nx = D->nx, ny = D->ny;
   const bool wall = D->wall != 0;
   // bytes between planes (the row pitch, the same in every group) and
@@ -420,22 +431,22 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
       }
     }
     // density, relaxation, forces
-    Real rho = K.ra, grx = Real(0), gry = Real(0);
-    Real Fx = Real(0), Fy = Real(0), Jx = Real(0), Jy = Real(0);
+    Acc rho = KD.ra, grx = Acc(0), gry = Acc(0);
+    Acc Fx = Acc(0), Fy = Acc(0), Jx = Acc(0), Jy = Acc(0);
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-      rho += K.rA[i] * phi[i];
-      grx += K.rA[i] * gpx[i];
-      gry += K.rA[i] * gpy[i];
+      rho += KD.rA[i] * phi[i];
+      grx += KD.rA[i] * gpx[i];
+      gry += KD.rA[i] * gpy[i];
       Fx += Cv[i] * gpx[i];
       Fy += Cv[i] * gpy[i];
       if constexpr (!kR1) {
-        Jx += K.Jc[i] * gCx[i];
-        Jy += K.Jc[i] * gCy[i];
+        Jx += KD.Jc[i] * gCx[i];
+        Jy += KD.Jc[i] * gCy[i];
       }
     }
-    Fx += rho * K.gx;
-    Fy += rho * K.gy;
+    Fx += rho * KD.gx;
+    Fy += rho * KD.gy;
     if constexpr (kR1) {
       // Remark 1: F -= div(J~ u), (div)_x = d_x q0 + d_y q1,
       // (div)_y = d_x q2 + d_y q3, eq:N31a on the product ring; a row
@@ -448,68 +459,70 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
       const int sN = ghost(mC + dir) ? s0 : ring<kQR>(mC + dir);
       const int sS = ghost(mC - dir) ? s0 : ring<kQR>(mC - dir);
       auto ddx = [&](int c) {
-        return (Real(4) * (sQ[s0][c][lane + 1] - sQ[s0][c][lane - 1]) +
+        return (Acc(4) * (sQ[s0][c][lane + 1] - sQ[s0][c][lane - 1]) +
                 ((sQ[sN][c][lane + 1] - sQ[sN][c][lane - 1]) +
                  (sQ[sS][c][lane + 1] - sQ[sS][c][lane - 1]))) *
-               (Real(1) / Real(12));
+               (Acc(1) / Acc(12));
       };
       auto ddy = [&](int c) {
-        return (Real(4) * (sQ[sN][c][lane] - sQ[sS][c][lane]) +
+        return (Acc(4) * (sQ[sN][c][lane] - sQ[sS][c][lane]) +
                 ((sQ[sN][c][lane + 1] + sQ[sN][c][lane - 1]) -
                  (sQ[sS][c][lane + 1] + sQ[sS][c][lane - 1]))) *
-               (Real(1) / Real(12));
+               (Acc(1) / Acc(12));
       };
       Fx -= ddx(0) + ddy(1);
       Fy -= ddx(2) + ddy(3);
     }
-    Real itau, srcg, theta;
-    if (K.const_tau) {
-      itau = K.itau_g;
-      srcg = K.src_g;
-      theta = K.theta_g;
+    Acc itau, srcg, theta;
+    if (KD.const_tau) {
+      itau = KD.itau_g;
+      srcg = KD.src_g;
+      theta = KD.theta_g;
     } else {
-      Real mu = K.ma;
+      Acc mu = KD.ma;
 #pragma unroll
-      for (int i = 0; i < M; ++i) mu += K.mA[i] * phi[i];
+      for (int i = 0; i < M; ++i) mu += KD.mA[i] * phi[i];
       // tau_g = 1/2 + mu / (rho c_s^2)  (eq:N21_1 with nu = mu / rho)
-      const Real tm = Real(3) * mu / rho;  // tau_g - 1/2
-      itau = Real(1) / (Real(0.5) + tm);
-      srcg = Real(1) - Real(0.5) * itau;
-      theta = Real(1) / tm;
+      const Acc tm = Acc(3) * mu / rho;  // tau_g - 1/2
+      itau = Acc(1) / (Acc(0.5) + tm);
+      srcg = Acc(1) - Acc(0.5) * itau;
+      theta = Acc(1) / tm;
     }
-    const Real(&g)[9] = Q.g;
-    const Real irho = Real(1) / rho;
-    const Real mx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
-    const Real my = (g[2] - g[4]) + (g[5] + g[6]) - (g[7] + g[8]);
-    const Real ux = (mx + Real(0.5) * Fx) * irho;  // eq:N22_1
-    const Real uy = (my + Real(0.5) * Fy) * irho;
-    Real sumg = g[1];
+    Acc g[9];
+#pragma unroll
+    for (int k = 1; k < 9; ++k) g[k] = Q.g[k];
+    const Acc irho = Acc(1) / rho;
+    const Acc mx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
+    const Acc my = (g[2] - g[4]) + (g[5] + g[6]) - (g[7] + g[8]);
+    const Acc ux = (mx + Acc(0.5) * Fx) * irho;  // eq:N22_1
+    const Acc uy = (my + Acc(0.5) * Fy) * irho;
+    Acc sumg = g[1];
 #pragma unroll
     for (int k = 2; k < 9; ++k) sumg += g[k];
-    const Real usq = ux * ux + uy * uy;
-    const Real udr = ux * grx + uy * gry;
+    const Acc usq = ux * ux + uy * uy;
+    const Acc udr = ux * grx + uy * gry;
     // eq:N23: p = c_s^2 / (1 - w_0) [sum_{k!=0} g_k + u.grad(rho)/2 + rho s_0(u)]
-    const Real p = Real(0.6) * (sumg + Real(0.5) * udr - Real(2) / Real(3) * rho * usq);
-    const Real uF = ux * Fx + uy * Fy;
-    const Real Ju = Jx * ux + Jy * uy;
+    const Acc p = Acc(0.6) * (sumg + Acc(0.5) * udr - Acc(2) / Acc(3) * rho * usq);
+    const Acc uF = ux * Fx + uy * Fy;
+    const Acc Ju = Jx * ux + Jy * uy;
     // isotropic part of eq:N20_1: u.grad(rho) - tr(T) / (2 c_s^2)
-    const Real gbase =
-        udr - Real(1.5) * (Real(2) * uF + Real(2) / Real(3) * udr + (kR1 ? Real(0) : theta * Ju));
+    const Acc gbase =
+        udr - Acc(1.5) * (Acc(2) * uF + Acc(2) / Acc(3) * udr + (kR1 ? Acc(0) : theta * Ju));
     const Rsrc wh = row_rsrc(hd, rbh, yp), wg = row_rsrc(gd, rbg, yp),
                wp = row_rsrc(pvd, rbp, yp);
 #pragma unroll
     for (int k = 1; k < 9; ++k) {
-      const Real cx = Real(cxk(k)), cy = Real(cyk(k));
-      const Real w = wk<Real>(k);
-      const Real cu = cx * ux + cy * uy;
-      const Real cF = cx * Fx + cy * Fy;
-      const Real cr = cx * grx + cy * gry;
-      const Real cJ = cx * Jx + cy * Jy;
-      const Real geq =
-          w * (Real(3) * p + rho * (Real(3) * cu + Real(4.5) * cu * cu - Real(1.5) * usq));
-      const Real G =
-          w * (gbase + Real(3) * cF +
-               Real(4.5) * cu * (Real(2) * cF + Real(2) / Real(3) * cr + (kR1 ? Real(0) : theta * cJ)));
+      const Acc cx = Acc(cxk(k)), cy = Acc(cyk(k));
+      const Acc w = wk<Acc>(k);
+      const Acc cu = cx * ux + cy * uy;
+      const Acc cF = cx * Fx + cy * Fy;
+      const Acc cr = cx * grx + cy * gry;
+      const Acc cJ = cx * Jx + cy * Jy;
+      const Acc geq =
+          w * (Acc(3) * p + rho * (Acc(3) * cu + Acc(4.5) * cu * cu - Acc(1.5) * usq));
+      const Acc G =
+          w * (gbase + Acc(3) * cF +
+               Acc(4.5) * cu * (Acc(2) * cF + Acc(2) / Acc(3) * cr + (kR1 ? Acc(0) : theta * cJ)));
       bst<Real>(wg, xcu, (uint32_t)(k - 1) * pb, g[k] - itau * (g[k] - geq) + srcg * G);
     }
     // CH collisions
