@@ -52,7 +52,11 @@ enum {
  *   nx, ny          lattice size, each >= 4
  *   wall_y          0: periodic in y; 1: halfway bounce-back walls below
  *                   row 0 and above row ny-1 (Sec. 4.2). x is periodic.
- *   precision       32 or 64: arithmetic and storage type of the state
+ *   precision       32 or 64: storage type of the state and arithmetic
+ *                   type of the stencils and CH collisions; the NS
+ *                   collision is evaluated in FP64 arithmetic in both
+ *                   (FP32 rounding there biases the momentum of moving
+ *                   droplets).  FP32 stores deviations from the rest state.
  *   grad_scheme     first derivatives of phi_i and C_i: 0 = isotropic
  *                   central stencil of eq:N31a; 1 = isotropic mixed
  *                   stencil of eq:N40 (Sec. 4.4) with its two-hop term
