@@ -46,3 +46,25 @@ def test_random_fp32_vs_fp64(N, wall):
     d64.step(1000)
     assert np.max(np.abs(d32.get_c() - d64.get_c())) < 1e-5
     assert np.max(np.abs(d32.get_u() - d64.get_u())) < 1e-6
+
+
+def test_moving_droplets_fp32_gap_does_not_grow():
+    """The N = 4 collision layout at 256^2 (droplets moving at 0.01): the
+    FP32 - FP64 gap on c after 4000 steps is within 1e-5 and no more than
+    four times the gap after 1000 steps (with the NS collision evaluated in
+    FP32 arithmetic it grew as t^2)."""
+    w = W.droplet_collision(256, accept=oracle_accepts)
+    print(f"case {w.name} 256^2 fp32 vs fp64 steps=4000", flush=True)
+    a = gpu_domain(w, precision=64)
+    b = gpu_domain(w, precision=32)
+    a.step(1000)
+    b.step(1000)
+    e1 = float(np.max(np.abs(a.get_c() - b.get_c())))
+    a.step(3000)
+    b.step(3000)
+    e4 = float(np.max(np.abs(a.get_c() - b.get_c())))
+    a.close()
+    b.close()
+    print(f"  |c32 - c64|: {e1:.2e} after 1000 steps, {e4:.2e} after 4000", flush=True)
+    assert e4 < 1e-5
+    assert e4 < 4 * e1 + 1e-7

@@ -416,6 +416,34 @@ def static_sphere(n: int = 64, R: float = 16.0, W: float = 4.0, sigma: float = 1
                     tau_phi=0.8, W=W, steps=steps, precision=precision, nz=n)
 
 
+def droplet_collision3d(side: int = 64, W: float = 4.0, seed: int = BASE_SEED + 6,
+                        accept=None, precision: int = 32, steps: int = 2000,
+                        speed: float = 0.01) -> Workload:
+    """3-D counterpart of droplet_collision: N=4 in a periodic side^3 box;
+    phases 2, 3, 4 are spheres of radius 10/64 * side at (0.25, 0.5, 0.4),
+    (0.75, 0.5, 0.4) and (0.5, 0.5, 0.8) of the box moving with (+v, 0, 0),
+    (-v, 0, 0) and (0, 0, -v); u = sum_d c_d v_d; sigma_kl ~ U[0.5e-3,
+    2e-3], rho_1 = 1, rho_2..4 ~ U[1, 3], mu_k = 0.1 rho_k."""
+    x, y, z = grid3(side, side, side)
+    R = 10.0 * side / 64.0
+    centres = [(0.25, 0.5, 0.4, (speed, 0.0, 0.0)), (0.75, 0.5, 0.4, (-speed, 0.0, 0.0)),
+               (0.5, 0.5, 0.8, (0.0, 0.0, -speed))]
+    cs, u = [], np.zeros((3,) + x.shape)
+    for fx, fy, fz, v in centres:
+        r = np.sqrt((x - fx * side) ** 2 + (y - fy * side) ** 2 + (z - fz * side) ** 2)
+        cd = _profile(R - r, W)
+        cs.append(cd)
+        for d in range(3):
+            u[d] += cd * v[d]
+    c = np.stack([1.0 - sum(cs)] + cs)
+    rng = np.random.default_rng(seed + 1000)
+    rho = np.concatenate([[1.0], rng.uniform(1.0, 3.0, size=3)])
+    sigma, redraws = draw_sigma(4, seed, accept=accept, rho=rho)
+    return Workload("droplet_collision3d_N4", 4, side, side, sigma, rho, 0.1 * rho, c, u,
+                    mobility=0.1, tau_phi=0.8, W=W, steps=steps, precision=precision, nz=side,
+                    note=f"sigma redraws={redraws}")
+
+
 def slabs_and_spheres(side: int = 256, ndrop: int = 64, W: float = 4.0,
                       seed: int = BASE_SEED + 5, accept=None, precision: int = 32,
                       steps: int = 20000, rmin: float = 6.0, rmax: float = 20.0) -> Workload:
