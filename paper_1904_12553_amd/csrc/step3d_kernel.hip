@@ -364,8 +364,10 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
     // not store
     const int ln = col;
     Real phi[M], Cv[M];
-    Acc rho = KD.ra, gr[3] = {Acc(0), Acc(0), Acc(0)}, F[3] = {Acc(0), Acc(0), Acc(0)},
-         J[3] = {Acc(0), Acc(0), Acc(0)};
+    // (the sums over phases of the gradient terms stay in the state type)
+    Acc rho = KD.ra;
+    Real grs[3] = {Real(0), Real(0), Real(0)}, Fs[3] = {Real(0), Real(0), Real(0)},
+         Js[3] = {Real(0), Real(0), Real(0)};
 #pragma unroll
     for (int i = 0; i < M; ++i) {
       phi[i] = sphi[s0][i][pr][ln];
@@ -376,11 +378,13 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
       rho += KD.rA[i] * phi[i];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        gr[d] += KD.rA[i] * gp[d];
-        F[d] += Cv[i] * gp[d];
-        J[d] += KD.Jc[i] * gc[d];
+        grs[d] += K.rA[i] * gp[d];
+        Fs[d] += Cv[i] * gp[d];
+        Js[d] += K.Jc[i] * gc[d];
       }
     }
+    const Acc gr[3] = {grs[0], grs[1], grs[2]}, J[3] = {Js[0], Js[1], Js[2]};
+    Acc F[3] = {Fs[0], Fs[1], Fs[2]};
     F[0] += rho * KD.gx;
     F[1] += rho * KD.gy;
     F[2] += rho * KD.gz;

@@ -431,20 +431,24 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
       }
     }
     // density, relaxation, forces
-    Acc rho = KD.ra, grx = Acc(0), gry = Acc(0);
-    Acc Fx = Acc(0), Fy = Acc(0), Jx = Acc(0), Jy = Acc(0);
+    // (the sums over phases of the gradient terms stay in the state type:
+    // measured, FP64 there changes nothing)
+    Acc rho = KD.ra;
+    Real grs = Real(0), gys = Real(0), Fxs = Real(0), Fys = Real(0), Jxs = Real(0), Jys = Real(0);
 #pragma unroll
     for (int i = 0; i < M; ++i) {
       rho += KD.rA[i] * phi[i];
-      grx += KD.rA[i] * gpx[i];
-      gry += KD.rA[i] * gpy[i];
-      Fx += Cv[i] * gpx[i];
-      Fy += Cv[i] * gpy[i];
+      grs += K.rA[i] * gpx[i];
+      gys += K.rA[i] * gpy[i];
+      Fxs += Cv[i] * gpx[i];
+      Fys += Cv[i] * gpy[i];
       if constexpr (!kR1) {
-        Jx += KD.Jc[i] * gCx[i];
-        Jy += KD.Jc[i] * gCy[i];
+        Jxs += K.Jc[i] * gCx[i];
+        Jys += K.Jc[i] * gCy[i];
       }
     }
+    const Acc grx = grs, gry = gys, Jx = Jxs, Jy = Jys;
+    Acc Fx = Fxs, Fy = Fys;
     Fx += rho * KD.gx;
     Fy += rho * KD.gy;
     if constexpr (kR1) {
