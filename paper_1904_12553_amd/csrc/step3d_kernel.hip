@@ -426,19 +426,26 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
     if (!lane_int) return;
     const Rsrc wh = row_rsrc(hd, plh, zp), wg = row_rsrc(gd, plg, zp),
                wp = row_rsrc(pvd, plp, zp);
+    // eq:24 with g^eq and G split into the parts even and odd in c_k, each
+    // pair of opposite directions evaluated once
+    const Acc keep = Acc(1) - itau;
+    const Acc e0 = Acc(3) * p - Acc(1.5) * rho * usq;
 #pragma unroll
     for (int k = 1; k < 15; ++k) {
+      if (opp3(k) < k) continue;
+      const int ko = opp3(k);
       const Acc cx = Acc(ex3(k)), cy = Acc(ey3(k)), cz = Acc(ez3(k));
       const Acc w = w3<Acc>(k);
       const Acc cu = cx * u[0] + cy * u[1] + cz * u[2];
       const Acc cF = cx * F[0] + cy * F[1] + cz * F[2];
       const Acc cr = cx * gr[0] + cy * gr[1] + cz * gr[2];
       const Acc cJ = cx * J[0] + cy * J[1] + cz * J[2];
-      const Acc geq =
-          w * (Acc(3) * p + rho * (Acc(3) * cu + Acc(4.5) * cu * cu - Acc(1.5) * usq));
-      const Acc G = w * (gbase + Acc(3) * cF +
-                          Acc(4.5) * cu * (Acc(2) * cF + Acc(2) / Acc(3) * cr + theta * cJ));
-      bst<Real>(wg, xcu, ybg[1] + (uint32_t)(k - 1) * pb, g[k] - itau * (g[k] - geq) + srcg * G);
+      const Acc ev =
+          w * (itau * (e0 + Acc(4.5) * rho * cu * cu) +
+               srcg * (gbase + Acc(4.5) * cu * (Acc(2) * cF + Acc(2) / Acc(3) * cr + theta * cJ)));
+      const Acc od = w * Acc(3) * (itau * rho * cu + srcg * cF);
+      bst<Real>(wg, xcu, ybg[1] + (uint32_t)(k - 1) * pb, keep * g[k] + ev + od);
+      bst<Real>(wg, xcu, ybg[1] + (uint32_t)(ko - 1) * pb, keep * g[ko] + ev - od);
     }
 #pragma unroll
     for (int i = 0; i < M; ++i) {

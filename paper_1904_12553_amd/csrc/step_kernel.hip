@@ -514,20 +514,30 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
         udr - Acc(1.5) * (Acc(2) * uF + Acc(2) / Acc(3) * udr + (kR1 ? Acc(0) : theta * Ju));
     const Rsrc wh = row_rsrc(hd, rbh, yp), wg = row_rsrc(gd, rbg, yp),
                wp = row_rsrc(pvd, rbp, yp);
+    // g* = (1 - 1/tau) g + g^eq / tau + (1 - 1/(2 tau)) G (eq:24), with
+    // g^eq (eq:25) and G (eq:N20_1) split into the parts even and odd in
+    // c_k: opposite directions share the even part and negate the odd one,
+    // so each pair is evaluated once
+    const Acc keep = Acc(1) - itau;
+    const Acc e0 = Acc(3) * p - Acc(1.5) * rho * usq;
 #pragma unroll
     for (int k = 1; k < 9; ++k) {
+      if (oppk(k) < k) continue;
+      const int ko = oppk(k);
       const Acc cx = Acc(cxk(k)), cy = Acc(cyk(k));
       const Acc w = wk<Acc>(k);
       const Acc cu = cx * ux + cy * uy;
       const Acc cF = cx * Fx + cy * Fy;
       const Acc cr = cx * grx + cy * gry;
       const Acc cJ = cx * Jx + cy * Jy;
-      const Acc geq =
-          w * (Acc(3) * p + rho * (Acc(3) * cu + Acc(4.5) * cu * cu - Acc(1.5) * usq));
-      const Acc G =
-          w * (gbase + Acc(3) * cF +
-               Acc(4.5) * cu * (Acc(2) * cF + Acc(2) / Acc(3) * cr + (kR1 ? Acc(0) : theta * cJ)));
-      bst<Real>(wg, xcu, (uint32_t)(k - 1) * pb, g[k] - itau * (g[k] - geq) + srcg * G);
+      const Acc ev =
+          w * (itau * (e0 + Acc(4.5) * rho * cu * cu) +
+               srcg * (gbase + Acc(4.5) * cu *
+                                   (Acc(2) * cF + Acc(2) / Acc(3) * cr +
+                                    (kR1 ? Acc(0) : theta * cJ))));
+      const Acc od = w * Acc(3) * (itau * rho * cu + srcg * cF);
+      bst<Real>(wg, xcu, (uint32_t)(k - 1) * pb, keep * g[k] + ev + od);
+      bst<Real>(wg, xcu, (uint32_t)(ko - 1) * pb, keep * g[ko] + ev - od);
     }
     // CH collisions
     const Real pux = Q.pu[0], puy = Q.pu[1];
