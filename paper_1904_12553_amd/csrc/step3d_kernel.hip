@@ -462,16 +462,25 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
       }
       const Real ec = K.eta_i[i] * Cv[i];
       const Real it = K.itau_i[i], sr = K.src_i[i];
+      // eq:N24 with h^eq (eq:N25) and R_k (eq:N26) split into the parts
+      // even and odd in c_k, per pair of opposite directions
+      const Real keep = Real(1) - it;
       Real hsum = Real(0);
 #pragma unroll
       for (int k = 1; k < 15; ++k) {
+        if (opp3(k) < k) continue;
+        const int ko = opp3(k);
         const Real cx = Real(ex3(k)), cy = Real(ey3(k)), cz = Real(ez3(k));
         const Real w = w3<Real>(k);
-        const Real heq = w * (ec + Real(3) * (cx * ps[0] + cy * ps[1] + cz * ps[2]));  // eq:N25
-        const Real R = sr * w * Real(3) * (cx * dd[0] + cy * dd[1] + cz * dd[2]);     // eq:N26
-        const Real hn = P.h[i][k] - it * (P.h[i][k] - heq) + R;
-        hsum += hn;
+        const Real ev = it * w * ec;
+        const Real od = w * Real(3) *
+                        (it * (cx * ps[0] + cy * ps[1] + cz * ps[2]) +
+                         sr * (cx * dd[0] + cy * dd[1] + cz * dd[2]));
+        const Real hn = keep * P.h[i][k] + ev + od;
+        const Real ho = keep * P.h[i][ko] + ev - od;
+        hsum += hn + ho;
         bst<Real>(wh, xcu, ybh[1] + (uint32_t)(i * 15 + k) * pb, hn);
+        bst<Real>(wh, xcu, ybh[1] + (uint32_t)(i * 15 + ko) * pb, ho);
       }
       // phi_i = pp + lo exactly; fl(phi_i) is stored as the new previous
       // phi and the k = 0 slot keeps (pp + lo - fl(phi_i)) - sum h_k

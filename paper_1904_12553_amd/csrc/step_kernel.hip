@@ -548,16 +548,24 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
       const Real dx = psx - pp * pux, dy = psy - pp * puy;  // eq:N27
       const Real ec = K.eta_i[i] * Cv[i];
       const Real it = K.itau_i[i], sr = K.src_i[i];
+      // h* = (1 - 1/tau_i) h + h^eq / tau_i + R_k with h^eq (eq:N25) and R_k
+      // (eq:N26) split into the parts even and odd in c_k, per pair of
+      // opposite directions
+      const Real keep = Real(1) - it;
       Real hsum = Real(0);
 #pragma unroll
       for (int k = 1; k < 9; ++k) {
+        if (oppk(k) < k) continue;
+        const int ko = oppk(k);
         const Real cx = Real(cxk(k)), cy = Real(cyk(k));
         const Real w = wk<Real>(k);
-        const Real heq = w * (ec + Real(3) * (cx * psx + cy * psy));   // eq:N25
-        const Real R = sr * w * Real(3) * (cx * dx + cy * dy);         // eq:N26
-        const Real hn = P.h[i][k] - it * (P.h[i][k] - heq) + R;
-        hsum += hn;
+        const Real ev = it * w * ec;
+        const Real od = w * Real(3) * (it * (cx * psx + cy * psy) + sr * (cx * dx + cy * dy));
+        const Real hn = keep * P.h[i][k] + ev + od;
+        const Real ho = keep * P.h[i][ko] + ev - od;
+        hsum += hn + ho;
         bst<Real>(wh, xcu, (uint32_t)(i * 9 + k) * pb, hn);
+        bst<Real>(wh, xcu, (uint32_t)(i * 9 + ko) * pb, ho);
       }
       // phi_i = hi + lo exactly; phi[i] = fl(hi + lo) is stored as the new
       // previous phi and the k = 0 slot keeps (hi + lo - phi[i]) - sum h_k
