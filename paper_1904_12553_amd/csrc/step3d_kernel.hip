@@ -633,11 +633,11 @@ int occ3(int precision) {
 
 }  // namespace
 
-// Interior rows of a tile = waves of a workgroup: 8 for N <= 3, 4 for
-// N >= 4 (there FP64 rings of 8 rows would not fit in LDS, and in FP32 two
-// 4-row workgroups per CU measured faster than one of 8: 38% against 36% of
-// the HBM roofline on the N = 5 256^3 workload).  NPLBM_TY3 = 4 or 8
-// overrides.
+// Interior rows of a tile = waves of a workgroup: 4 in FP32, where two or
+// more 4-row workgroups per CU measured faster than one of 8 (256^3: N = 3
+// 48.3% against 44.9% of the HBM roofline, N = 5 38.2% against 35.6%); in
+// FP64 8 for N <= 3 (44.9% against 43.9% at N = 3) and 4 for N >= 4, where
+// FP64 rings of 8 rows would not fit in LDS.  NPLBM_TY3 = 4 or 8 overrides.
 int step3_ty(int N, int precision) {
   if (const char *e = std::getenv("NPLBM_TY3")) {
     const int t = std::atoi(e);
@@ -645,7 +645,7 @@ int step3_ty(int N, int precision) {
     const int lds = (k3PR * (t + 4) + k3CR * (t + 2)) * (N - 1) * k3L * bytes;
     if (t == 4 || (t == 8 && lds <= 160 * 1024)) return t;
   }
-  return N >= 4 ? 4 : 8;
+  return precision == 64 && N <= 3 ? 8 : 4;
 }
 
 hipError_t launch_step3(int N, int precision, int ty, const StepArgs &a, int nblocks, int nx,
