@@ -30,6 +30,9 @@ using namespace nplbm;
 
 namespace {
 
+// side streams of the quantum graph (groups beyond this share them)
+constexpr int kSideStreams = 4;
+
 double now_s() {
   using namespace std::chrono;
   return duration<double>(steady_clock::now().time_since_epoch()).count();
@@ -75,6 +78,11 @@ struct nplbm_server {
     size_t off, count;
   };
   std::vector<Group> groups;
+  // side streams and events of the quantum graph: each group's chain of
+  // launches is captured on its own stream, so the groups run side by side
+  std::vector<hipStream_t> side;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
   hipGraphExec_t graph = nullptr;
   bool dirty = true;
   double node_updates = 0, busy = 0;
@@ -200,21 +208,55 @@ int rebuild(nplbm_server *s) {
   hipError_t e = hipMemcpyAsync(s->strips_dev, all.data(), all.size() * sizeof(StripDesc),
                                 hipMemcpyHostToDevice, s->stream);
   if (e != hipSuccess) return hip_fail(e, "strip table upload");
+  // Groups touch disjoint domains and strip tables, so their chains of
+  // launches are independent: with more than one group, each chain is
+  // captured on a side stream forked from and joined back to the server's
+  // stream, and the graph runs the groups concurrently (a small group no
+  // longer leaves the GPU half idle for a whole launch).
+  const int ngr = (int)s->groups.size();
+  const int nside = ngr > 1 ? std::min(ngr, kSideStreams) : 0;
+  while ((int)s->side.size() < nside) {
+    hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
+    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      if (st) (void)hipStreamDestroy(st);
+      return hip_fail(e, "side stream creation");
+    }
+    s->side.push_back(st);
+    s->join.push_back(ev);
+  }
+  if (nside && !s->fork) {
+    e = hipEventCreateWithFlags(&s->fork, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "event creation");
+  }
   hipGraph_t g = nullptr;
   e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
   hipError_t le = hipSuccess;
+  if (nside) {
+    le = hipEventRecord(s->fork, s->stream);
+    for (int j = 0; j < nside && le == hipSuccess; ++j)
+      le = hipStreamWaitEvent(s->side[j], s->fork, 0);
+  }
   for (int q = 0; q < s->quantum && le == hipSuccess; ++q)
-    for (auto &gr : s->groups) {
+    for (int gi = 0; gi < ngr; ++gi) {
+      const auto &gr = s->groups[gi];
       StepArgs a;
       std::memset(&a, 0, sizeof a);
       a.strips = s->strips_dev + gr.off;
       a.doms = s->descs_dev;
       a.substep = q;
       le = launch_step(gr.N, gr.precision, gr.scheme,
-                       step_geom(gr.N, gr.precision, gr.scheme).bw, a, (int)gr.count, s->stream);
+                       step_geom(gr.N, gr.precision, gr.scheme).bw, a, (int)gr.count,
+                       nside ? s->side[gi % nside] : s->stream);
       if (le != hipSuccess) break;
     }
+  for (int j = 0; j < nside && le == hipSuccess; ++j) {
+    le = hipEventRecord(s->join[j], s->side[j]);
+    if (le == hipSuccess) le = hipStreamWaitEvent(s->stream, s->join[j], 0);
+  }
   e = hipStreamEndCapture(s->stream, &g);
   if (le != hipSuccess) {
     if (g) (void)hipGraphDestroy(g);
@@ -469,6 +511,9 @@ void nplbm_server_destroy(nplbm_server *s) {
   if (s->graph) (void)hipGraphExecDestroy(s->graph);
   if (s->strips_dev) (void)hipFree(s->strips_dev);
   if (s->descs_dev) (void)hipFree(s->descs_dev);
+  for (hipStream_t st : s->side) (void)hipStreamDestroy(st);
+  for (hipEvent_t ev : s->join) (void)hipEventDestroy(ev);
+  if (s->fork) (void)hipEventDestroy(s->fork);
   delete s;
 }
 
