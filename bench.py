@@ -25,6 +25,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -42,10 +43,16 @@ def log(*a):
 
 
 def kernel_hash():
+    """Hash of the step kernel's code (its sources with comments and
+    whitespace removed), so that the committed counter record is used only
+    for the code it was taken on."""
     h = hashlib.sha256()
     for f in ("step_kernel.hip", "buffer_io.h", "nplbm_internal.h", "lattice.h"):
-        with open(os.path.join(ROOT, "paper_1904_12553_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1904_12553_amd", "csrc", f)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -148,15 +148,16 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   const void *gs = D->g[par], *gd = D->g[par ^ 1];
   const void *pvs = D->prev[par], *pvd = D->prev[par ^ 1];
   const NPL_CONST Consts<Real> &K = *consts_of<Real>(D);
-  // The NS part of the collision (density, forces, u, p, g^eq, G and the
-  // g update) is evaluated in FP64 arithmetic in both modes; the FP32 mode
-  // still stores FP32 populations.  Evaluated in FP32, the rounding of g^eq
+  // The NS part of the collision (density, u, p, g^eq, G and the g update)
+  // is evaluated in FP64 arithmetic in both modes; the FP32 mode still
+  // stores FP32 populations.  Evaluated in FP32, the rounding of g^eq
   // and of the update leaves each node's momentum off by a fraction of an
   // ulp, in the same direction wherever the flow state repeats (inside a
   // moving droplet), so droplets gain momentum steadily and interfaces drift
   // as t^2: FP32 vs FP64 on the 512^2 N = 4 droplet collision went from
   // 2.6e-5 to 7e-8 in c after 2000 steps (2e-3 to 7e-7 after 50000), for
-  // 2.7% more kernel time.
+  // 2.7% more kernel time, most of which the evaluation per pair of
+  // opposite directions below won back.
   using Acc = double;
   const NPL_CONST Consts<double> &KD = *consts_of<double>(D);
   const int nx = D->nx, ny = D->ny;
