@@ -292,16 +292,21 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   };
 
   // ---- stage B: chemical potentials for march index mB -> LDS ----
-  // C is needed on the interior columns and one (central) or two (mixed)
-  // columns either side.  Next to a wall, C of a ghost row is the mirror of
-  // C inside: the central scheme reads it from the row it mirrors (C(-1) =
-  // C(0)); the mixed scheme needs two ghost rows, C(-2) = C(1) being ahead
-  // of the march, and evaluates them on the mirrored phi rows the ring
-  // holds, which gives the same values (the stencil is mirror-symmetric).
+  // C is needed on the interior columns and one (central) or two (mixed,
+  // Remark 1) columns either side.  Next to a wall, C of a ghost row is the
+  // mirror of C inside.  The central scheme reads it from the row it
+  // mirrors (C(-1) = C(0)).  The other two evaluate ghost rows on the
+  // mirrored phi rows the ring holds, which gives the same values (the
+  // stencil is mirror-symmetric): the mixed scheme needs two ghost rows,
+  // C(-2) = C(1) being ahead of the march, and Remark 1 needs the ghost C
+  // for J~ on the wall row, which a strip marching away from the wall may
+  // hold in its ramp; there the row it mirrors can be one whose phi
+  // neighbour the march has not pulled yet (a strip starting one row
+  // inside the wall).
   auto stageB = [&](int mB) {
     if (lane < 1 || lane > ncol + 2 * kHalo - 2) return;
     int me = mB;
-    if (!kTwoHop && wall) {
+    if (kGS == 0 && wall) {
       const int r = row_of(mB);
       if (r < 0) me = mB + dir;          // ghost below row 0: C(-1) = C(0)
       else if (r >= ny) me = mB - dir;   // ghost above row ny-1

@@ -114,3 +114,24 @@ def test_remark1_serving_alone_equals_mix():
         d.close()
         for x, y in zip(results[t][:3], alone):
             assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("N,ny", [(2, 33), (4, 33), (5, 65)])
+@pytest.mark.parametrize("gs,ff", [(0, 1), (1, 0), (0, 0)])
+def test_strip_starting_one_row_inside_the_top_wall(N, ny, gs, ff, monkeypatch):
+    """16-row strips on ny = 16 k + 1 rows: the strip below the last one
+    marches down from one row inside the top wall, so its ramp holds the
+    wall row and then ghost rows.  Remark 1 needs C on the ghost row for J~
+    on the wall row; taking it from the row it mirrors read a phi row not
+    yet pulled (1e-6 off after one step) until ghost rows were evaluated on
+    the mirrored phi rows."""
+    monkeypatch.setenv("NPLBM_MIN_STRIP_H", "16")
+    w = W.random_smooth(N, 100, ny, seed=8001, wall_y=True, accept=oracle_accepts, W=4.73)
+    over = dict(grad_scheme=gs, force_form=ff)
+    print(f"case N={N} 100x{ny} walls {over} steps=25", flush=True)
+    o = oracle_run(w, 25, **over)
+    d = gpu_domain(w, **over)
+    d.step(25)
+    res = [maxabs(a, b) for a, b in zip(d.macro(), o.macro())]
+    d.close()
+    assert max(res) < TOL, res
