@@ -86,3 +86,53 @@ def test_server_in_a_fresh_process_that_loads_the_library_first():
     r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
                        timeout=200, env=dict(os.environ, PYTHONPATH=root))
     assert r.returncode == 0 and "server ok" in r.stdout, r.stdout + r.stderr
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_seeded_mixes_alone_equals_mix(seed):
+    """Seeded mixes of 8 requests over N = 2..8, the three schemes, both
+    precisions, periodic or walls, sides 20..150, 1..120 steps, arriving
+    in three waves (into a running mix, so groups appear and vanish between
+    quanta): every result bitwise equal to the request run alone."""
+    import paper_1904_12553_amd as P
+    rng = np.random.default_rng(300 + seed)
+    jobs = []
+    for i in range(8):
+        N = int(rng.integers(2, 9))
+        nx, ny = int(rng.integers(20, 151)), int(rng.integers(8, 121))
+        wall = bool(rng.integers(0, 2))
+        sig = (0.5e-3, 2e-3) if N <= 5 else (0.8e-3, 1.2e-3)
+        w = W.random_smooth(N, nx, ny, seed=3000 + 10 * seed + i, wall_y=wall,
+                            accept=P.accepts, sigma_range=sig)
+        over = [{}, {"grad_scheme": 1}, {"force_form": 1}][int(rng.integers(0, 3))]
+        prec = int(rng.choice([32, 64]))
+        steps = int(rng.integers(1, 121))
+        jobs.append((w, over, prec, steps))
+    print(f"case seeded mix {seed}: " + ", ".join(
+        f"N={w.N} {w.nx}x{w.ny} {o} fp{p} {s}" for w, o, p, s in jobs), flush=True)
+    srv = P.Server(hbm_budget=1 << 31, max_slots=6, quantum=20)
+    tickets = {}
+    for wave in (jobs[:3], jobs[3:6], jobs[6:]):
+        for w, over, prec, steps in wave:
+            tickets[srv.submit(w.c, w.u, nsteps=steps, precision=prec,
+                               **dict(w.params(), **over))] = (w, over, prec, steps)
+        srv.pump()
+    results = {}
+    for _ in range(2000):
+        srv.pump()
+        for t in tickets:
+            if t not in results and srv.poll(t) == 2:
+                results[t] = srv.result(t)
+        if len(results) == len(tickets):
+            break
+    srv.close()
+    assert len(results) == len(tickets)
+    for t, (w, over, prec, steps) in tickets.items():
+        d = P.Domain(precision=prec, **dict(w.params(), **over))
+        d.set_fields(w.c, w.u)
+        d.step(steps)
+        ca, ua, pa = d.macro()
+        d.close()
+        c, u, p, _, _ = results[t]
+        assert np.array_equal(c, ca) and np.array_equal(u, ua) and np.array_equal(p, pa), \
+            (w.N, w.nx, w.ny, over, prec, steps)
