@@ -52,6 +52,8 @@ int64_t plane_pad(size_t elem);
 // default padding of every row block of the row-interleaved layout
 constexpr size_t kRowPadBytes = 0;
 int64_t row_pad(size_t elem);
+// elements between the planes of one lattice row (the padded row pitch)
+int64_t state_pitch(const nplbm_params *p);
 // step-kernel scheme (kSchemeCentral / kSchemeMixed / kSchemeRemark1) of a
 // validated parameter set
 int step_scheme(const nplbm_params *p);

@@ -107,8 +107,7 @@ int derive(const nplbm_params *p, Derived &d) {
     if (!std::isfinite(p->gz)) return fail(NPLBM_EINVAL, "gz must be finite");
     // the 3-D kernel addresses one plane of a state group (ny row blocks)
     // with 32-bit byte offsets below 2^31
-    if ((int64_t)p->ny * 15 * (N - 1) * (((int64_t)p->nx + 31) & ~(int64_t)31) *
-            (p->precision / 8) >= (int64_t)1 << 31)
+    if ((int64_t)p->ny * 15 * (N - 1) * state_pitch(p) * (p->precision / 8) >= (int64_t)1 << 31)
       return fail(NPLBM_EINVAL, "nx * ny too large for a 3-D domain: a plane would exceed 2^31 bytes");
   } else if (p->wall_z != 0 || p->gz != 0.0) {
     return fail(NPLBM_EINVAL, "wall_z and gz apply to 3-D domains (nz >= 4) only");
@@ -117,8 +116,7 @@ int derive(const nplbm_params *p, Derived &d) {
     return fail(NPLBM_EINVAL, "precision must be 32 or 64");
   // the step kernel addresses one row block of a state group (all its
   // planes of one lattice row) with 32-bit byte offsets below 2^31
-  if ((int64_t)(is3d(p) ? 15 : 9) * (N - 1) * (((int64_t)p->nx + 31) & ~(int64_t)31) *
-          (p->precision / 8) >=
+  if ((int64_t)(is3d(p) ? 15 : 9) * (N - 1) * state_pitch(p) * (p->precision / 8) >=
       (int64_t)1 << 31)
     return fail(NPLBM_EINVAL, "nx=%d too large: a row block would exceed 2^31 bytes", p->nx);
   if (p->grad_scheme != kGradCentral && p->grad_scheme != kGradMixed)
@@ -376,17 +374,24 @@ int single_domain_target(const nplbm_params *p) {
   return r > 0 ? r : 2048;
 }
 
+// Elements between the planes of one lattice row: nx rounded up to whole
+// 128-byte lines of FP32 (rows start on lines); in 3-D one extra line when
+// that is a multiple of 256 elements (256^3 N = 3 FP32: 40.5% against 38.8%
+// of the HBM roofline; 2-D measured no difference).  The validation bounds
+// the 32-bit offsets with this same pitch.
+int64_t state_pitch(const nplbm_params *p) {
+  int64_t pitch = ((int64_t)p->nx + 31) & ~(int64_t)31;
+  if (is3d(p) && pitch % 256 == 0) pitch += 32;
+  if (const char *e = std::getenv("NPLBM_PITCH_PAD")) pitch += std::max(0, std::atoi(e)) & ~31;
+  return pitch;
+}
+
 Layout plan_layout(const nplbm_params *p) {
   Layout L;
   const int N = p->N, M = N - 1;
   const size_t s = p->precision == 64 ? 8 : 4;
-  L.pitch = (p->nx + 31) & ~31;  // rows start on 128-byte lines
+  L.pitch = (int)state_pitch(p);
   const bool d3 = is3d(p);
-  // 3-D: one extra cache line per plane row when the pitch is a multiple of
-  // 256 elements (256^3 N = 3 FP32: 40.5% against 38.8% of the HBM roofline;
-  // 2-D measured no difference)
-  if (d3 && L.pitch % 256 == 0) L.pitch += 32;
-  if (const char *e = std::getenv("NPLBM_PITCH_PAD")) L.pitch += std::max(0, std::atoi(e)) & ~31;
   const int nrows = p->ny * dom_nz(p);  // (z, y) lines of nodes
   const size_t n = (size_t)p->nx * nrows;
   // planes per group: CH populations, NS populations k >= 1, previous phi and u

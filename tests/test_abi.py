@@ -161,3 +161,18 @@ def test_library_shares_torchs_hip_runtime():
     assert r.returncode == 0, r.stderr
     libs = eval(r.stdout.strip().splitlines()[-1])
     assert len(libs) == 1, libs
+
+
+def test_offset_limit_counts_the_padded_pitch():
+    """3-D rows whose width is a multiple of 256 elements get one extra
+    cache line of pitch; the 2^31-byte bound on a plane of a state group
+    must count it (16384 columns are stored with a pitch of 16416)."""
+    from paper_1904_12553_amd import nplbm
+    N = 3
+    kw = dict(N=N, nx=16384, nz=6, sigma=W.uniform_sigma(N, 1e-3), rho=np.ones(N),
+              mu=np.full(N, 0.1), wall_z=1)
+    ok_ny = (1 << 31) // (15 * (N - 1) * 16416 * 4)          # 1090 rows fit
+    assert 15 * (N - 1) * ok_ny * 16384 * 4 < 1 << 31
+    assert 15 * (N - 1) * (ok_ny + 1) * 16384 * 4 < 1 << 31  # unpadded: would fit
+    assert nplbm.footprint(precision=32, ny=ok_ny, **kw) > 0
+    assert nplbm.footprint(precision=32, ny=ok_ny + 1, **kw) == 0

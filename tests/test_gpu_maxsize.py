@@ -47,3 +47,29 @@ def test_largest_row_block_is_translation_invariant():
         a = a.reshape(a.shape[:-1] + (REPEAT, 100))
         assert (a == b[..., None, :]).all()
     assert bad == 0 and dev < 1e-12
+
+
+def test_largest_3d_plane_is_translation_invariant():
+    """D3Q15, N = 3 in FP32: one plane of the CH group is 30 planes x 1088
+    rows x 16416 (padded) columns x 4 bytes = 2.1433e9 bytes, just below the
+    2^31 bound of the 3-D kernel's 32-bit offsets; 6 planes with walls in z,
+    107 million nodes, 53 GB.  Fields of period 64 x 16 in x and y: bitwise
+    equal to the 64 x 16 x 6 run tiled."""
+    import paper_1904_12553_amd as P
+    rx, ry = 256, 68
+    small = W.random_smooth3d(3, 64, 16, 6, seed=78, wall_z=True, accept=oracle_accepts)
+    big = dataclasses.replace(small, nx=64 * rx, ny=16 * ry,
+                              c=np.tile(small.c, (1, 1, ry, rx)), u=np.tile(small.u, (1, 1, ry, rx)))
+    assert P.footprint(precision=32, **big.params()) > 0
+    print(f"case {big.nx}x{big.ny}x{big.nz} N=3 fp32 walls steps=10", flush=True)
+    d = gpu_domain(small, precision=32)
+    d.step(10)
+    ref = d.macro()
+    d.close()
+    d = gpu_domain(big, precision=32)
+    d.step(10)
+    out = d.macro()
+    d.close()
+    for a, b in zip(out, ref):
+        a = a.reshape(a.shape[:-2] + (ry, 16, rx, 64))
+        assert (a == b.reshape(b.shape[:-2] + (1, 16, 1, 64))).all()
