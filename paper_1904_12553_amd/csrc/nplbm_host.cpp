@@ -548,9 +548,27 @@ void build_tiles3(int nx, int ny, int nz, int dom, int ty, int target,
   split(ny, ty, ys);
   const int nxy = (int)((xs.size() - 1) * (ys.size() - 1));
   if (target <= 0) target = 1024;
-  int nsz = std::max(1, target / std::max(1, nxy));
-  int H = (nz + nsz - 1) / nsz;
-  H = std::max(H, std::min(nz, 8));
+  // z segments: the count that minimises the rounds of resident workgroups
+  // times the planes one workgroup marches (its 4-plane ramp included),
+  // with segments of at least 8 planes (or the whole depth).  Rounding the
+  // count down instead (nxy tiles per segment against `target`) could leave
+  // CUs idle: 192^3 N = 4 FP64 ran 144 workgroups on 256 CUs, at 29% of the
+  // HBM roofline against 39% with 7 segments.
+  const int hmin = std::min(nz, 8);
+  int nsz = 1;
+  double best = -1.0;
+  for (int k = 1; k <= nz; ++k) {
+    const int h = (nz + k - 1) / k;
+    if (h < hmin) break;
+    if ((nz + h - 1) / h != k) continue;  // the same segments as a smaller count
+    const int64_t rounds = ((int64_t)nxy * k + target - 1) / target;
+    const double t = (double)rounds * (h + 4);
+    if (best < 0.0 || t < best) {
+      best = t;
+      nsz = k;
+    }
+  }
+  const int H = (nz + nsz - 1) / nsz;
   nsz = (nz + H - 1) / H;
   for (int sz = 0; sz < nsz; ++sz)
     for (size_t iy = 0; iy + 1 < ys.size(); ++iy)

@@ -524,9 +524,10 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
   // March: iteration j pulls plane mA = j - 2, computes C of mA - 1 and
   // collides mA - 2, so J = H + 4 iterations cover the interior planes.
   // The collision's own pulls are issued before stage A where the registers
-  // allow it (held through two barriers); FP64 with N >= 4 would spill, so
-  // there they are issued at the collision.
-  constexpr bool kEarly = !(sizeof(Real) == 8 && N >= 4);
+  // allow it (held through two barriers); FP64 with N >= 3 spills that way,
+  // so there they are issued at the collision (256^3 N = 3 FP64: 49.9%
+  // against 44.9% of the HBM roofline; FP32 measured slower late).
+  constexpr bool kEarly = !(sizeof(Real) == 8 && N >= 3);
   const int J = H + 4;
   PhiRow fr;
   load_phi(-2, fr);
