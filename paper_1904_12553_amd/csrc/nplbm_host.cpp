@@ -444,15 +444,19 @@ Layout plan_layout(const nplbm_params *p) {
 
 // Strip geometry of the step kernel for a precision and scheme.
 // Interior widths are multiples of one 128-byte cache line of state values
-// (32 floats or 16 doubles), so no line is written by two workgroups; rows
-// of 256 threads for FP32 and 64 for FP64 measured fastest on gfx950.  The
-// halo is 2 columns for the central gradients and 3 for the two-hop ones
-// (eq:N40, or the divergence of Remark 1 taken of a product of gradients).
+// (32 floats or 16 doubles), so no line is written by two workgroups.  Rows
+// of 256 threads measured fastest on gfx950 in FP32, and in FP64 with the
+// central gradients for N <= 3 (4096^2: N = 2 64.7% of the HBM roofline
+// against 60.6% with 64-thread rows, N = 3 65.8% against 59.5%); FP64 with
+// N >= 4 or the two-hop schemes runs one wave per SIMD, where 64-thread rows
+// measured fastest (N = 4: 66.3% against 58.0%).  The halo is 2 columns for
+// the central gradients and 3 for the two-hop ones (eq:N40, or the
+// divergence of Remark 1 taken of a product of gradients).
 StepGeom step_geom(int N, int precision, int scheme) {
   StepGeom g;
   g.halo = scheme == kSchemeCentral ? 2 : 3;
   const int unit = precision == 64 ? 16 : 32;
-  g.bw = precision == 64 ? 64 : 256;
+  g.bw = precision == 64 ? (scheme == kSchemeCentral && N <= 3 ? 256 : 64) : 256;
   if (const char *e = std::getenv("NPLBM_BW")) {
     const int b = std::atoi(e);
     g.bw = (b == 128 || b == 256) ? b : 64;
