@@ -600,15 +600,17 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   //  - mixed and Remark 1, N <= 4: three sets (cur, mA - 2, mA - 4); the
   //    Remark 1 scheme runs stage J on rows mA - 2 behind a third barrier
   //    before the collision;
-  //  - mixed and Remark 1, N >= 5: three sets would spill or leave one wave
-  //    per SIMD, so
-  //    the collision row's CH populations are pulled a second time (from
-  //    L2 / MALL, 2 iterations after the first pull) and one set suffices.
-  //    Measured on the 2048^2 N = 5 workload: 45% of the HBM roofline in
-  //    FP32 against 37% with three sets (the re-read costs the central
-  //    scheme 13 points, so it is used only here).
+  //  - mixed and Remark 1, N >= 5 (except Remark 1 in FP32 at N = 5): three
+  //    sets would spill or leave one wave per SIMD, so the collision row's
+  //    CH populations are pulled a second time (from L2 / MALL, 2 iterations
+  //    after the first pull) and one set suffices.  Measured on the 2048^2
+  //    N = 5 workload, mixed scheme: 45% of the HBM roofline in FP32 against
+  //    37% with three sets (the re-read costs the central scheme 13 points,
+  //    so it is used only here).  Remark 1 in FP32 still fits three sets at
+  //    N = 5 (229 VGPRs, two waves per SIMD): 56.8% against 45.3% with the
+  //    second pull.
   constexpr int kRamp = S::kRamp, kLag = S::kLag;
-  constexpr bool kRepull = kGS != 0 && N >= 5;
+  constexpr bool kRepull = kGS != 0 && N >= 5 && !(kGS == 2 && sizeof(Real) == 4 && N == 5);
   const int J = (H + kRamp + kLag + 1) / 2;
   PulledNS<Real> ns;
   constexpr bool kPipeline = kGS == 0 && sizeof(Real) == 4 && N <= 5;
