@@ -136,3 +136,48 @@ def test_seeded_mixes_alone_equals_mix(seed):
         c, u, p, _, _ = results[t]
         assert np.array_equal(c, ca) and np.array_equal(u, ua) and np.array_equal(p, pa), \
             (w.N, w.nx, w.ny, over, prec, steps)
+
+
+def test_submit_from_threads_while_pumping():
+    """Four threads submit four requests each while the main thread pumps
+    (submit is thread-safe; the binding's foreign calls release the GIL):
+    every ticket is distinct, and every result is bitwise the request
+    alone."""
+    import threading
+
+    import paper_1904_12553_amd as P
+    rng = np.random.default_rng(77)
+    jobs = []
+    for i in range(16):
+        N = int(rng.integers(2, 6))
+        w = W.random_smooth(N, int(rng.integers(20, 90)), int(rng.integers(8, 60)),
+                            seed=4000 + i, wall_y=bool(i % 2), accept=P.accepts)
+        jobs.append((w, int(rng.integers(5, 60))))
+    print("case threaded submit 4 x 4", flush=True)
+    srv = P.Server(hbm_budget=1 << 31, max_slots=8, quantum=10)
+    tickets = [None] * len(jobs)
+
+    def submitter(k):
+        for i in range(k, len(jobs), 4):
+            w, steps = jobs[i]
+            tickets[i] = srv.submit(w.c, w.u, nsteps=steps, precision=32, **w.params())
+
+    threads = [threading.Thread(target=submitter, args=(k,)) for k in range(4)]
+    for t in threads:
+        t.start()
+    results = {}
+    for _ in range(3000):
+        srv.pump()
+        for t in tickets:
+            if t is not None and t not in results and srv.poll(t) == 2:
+                results[t] = srv.result(t)
+        if all(t is not None for t in tickets) and len(results) == len(jobs):
+            break
+    for t in threads:
+        t.join()
+    srv.close()
+    assert len(set(tickets)) == len(jobs) and len(results) == len(jobs)
+    for t, (w, steps) in zip(tickets, jobs):
+        ca, ua, pa = _alone(w, steps)
+        c, u, p, _, _ = results[t]
+        assert np.array_equal(c, ca) and np.array_equal(u, ua) and np.array_equal(p, pa)
