@@ -46,7 +46,9 @@ struct Req {
   bool has_u = false;
   int64_t nsteps = 0;
   int64_t done_steps = 0;
-  int state = 0;  // 0 queued, 1 resident, 2 done, 3 failed
+  // 0 queued, 1 resident, 2 done, 3 failed; written and read only under the
+  // server's mutex, after everything it publishes (results, times) is written
+  int state = 0;
   double t_submit = 0, t_admit = 0, t_done = 0;
   // resident
   Derived d;
@@ -90,11 +92,6 @@ struct nplbm_server {
 };
 
 namespace {
-
-int srv_fail_req(Req *r, int code) {
-  r->state = 3;
-  return code;
-}
 
 void release(nplbm_server *s, Req *r) {
   if (r->base) (void)hipFree(r->base);
@@ -162,7 +159,6 @@ int admit(nplbm_server *s, Req *r) {
   }
   std::vector<double>().swap(r->c);
   std::vector<double>().swap(r->u);
-  r->state = 1;
   r->t_admit = now_s();
   r->done_steps = 0;
   s->dirty = true;
@@ -295,11 +291,7 @@ int retire(nplbm_server *s, Req *r) {
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   release(s, r);
   s->dirty = true;
-  if (e != hipSuccess) {
-    r->state = 3;
-    return hip_fail(e, "retire");
-  }
-  r->state = 2;
+  if (e != hipSuccess) return hip_fail(e, "retire");
   r->t_done = now_s();
   s->completed += 1;
   return NPLBM_OK;
@@ -402,17 +394,16 @@ int nplbm_server_pump(nplbm_server *s, int32_t *active_out) {
   for (Req *r : cand) {
     if (nres >= s->max_slots) break;
     if (s->used + r->bytes > s->budget) continue;
-    int rc = admit(s, r);
+    const int rc = admit(s, r);
+    int state = rc ? 3 : 1;
+    if (!rc && r->nsteps == 0)
+      state = retire(s, r) ? 3 : 2;
+    else if (!rc)
+      ++nres;
     {
       std::lock_guard<std::mutex> lk(s->mu);
       s->queue.erase(std::find(s->queue.begin(), s->queue.end(), r));
-      if (rc) r->state = 3;
-    }
-    if (rc) continue;
-    ++nres;
-    if (r->nsteps == 0) {
-      retire(s, r);
-      --nres;
+      r->state = state;
     }
   }
   if (s->dirty) {
@@ -445,9 +436,9 @@ int nplbm_server_pump(nplbm_server *s, int32_t *active_out) {
       if (!r) continue;
       r->done_steps += std::min<int64_t>(s->quantum, r->nsteps - r->done_steps);
       if (r->done_steps >= r->nsteps) {
+        const int state = retire(s, r) ? 3 : 2;
         std::lock_guard<std::mutex> lk(s->mu);
-        int rc = retire(s, r);
-        if (rc) r->state = 3;
+        r->state = state;
       }
     }
   }

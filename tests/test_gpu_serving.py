@@ -140,9 +140,10 @@ def test_seeded_mixes_alone_equals_mix(seed):
 
 def test_submit_from_threads_while_pumping():
     """Four threads submit four requests each while the main thread pumps
-    (submit is thread-safe; the binding's foreign calls release the GIL):
-    every ticket is distinct, and every result is bitwise the request
-    alone."""
+    and a fifth thread polls every ticket (submit and poll are thread-safe;
+    the binding's foreign calls release the GIL): every ticket is distinct,
+    the states a ticket shows only move forward (queued, resident, done),
+    and every result is bitwise the request alone."""
     import threading
 
     import paper_1904_12553_amd as P
@@ -162,21 +163,47 @@ def test_submit_from_threads_while_pumping():
             w, steps = jobs[i]
             tickets[i] = srv.submit(w.c, w.u, nsteps=steps, precision=32, **w.params())
 
+    seen, errors = {}, []
+    stop = threading.Event()
+
+    def poller():
+        while not stop.is_set():
+            for t in list(tickets):
+                if t is None or seen.get(t, [None])[-1] in (2, "gone"):
+                    continue
+                try:
+                    st = srv.poll(t)
+                except P.NplbmError as e:   # result() already took it
+                    if e.code != -7:
+                        errors.append(e)
+                    st = "gone"
+                if seen.setdefault(t, [st])[-1] != st:
+                    seen[t].append(st)
+
     threads = [threading.Thread(target=submitter, args=(k,)) for k in range(4)]
+    threads.append(threading.Thread(target=poller, daemon=True))
     for t in threads:
         t.start()
     results = {}
-    for _ in range(3000):
-        srv.pump()
-        for t in tickets:
-            if t is not None and t not in results and srv.poll(t) == 2:
-                results[t] = srv.result(t)
-        if all(t is not None for t in tickets) and len(results) == len(jobs):
-            break
-    for t in threads:
-        t.join()
+    try:
+        for _ in range(3000):
+            srv.pump()
+            for t in tickets:
+                if t is not None and t not in results and srv.poll(t) == 2:
+                    results[t] = srv.result(t)
+            if all(t is not None for t in tickets) and len(results) == len(jobs):
+                break
+    finally:
+        stop.set()
+        for t in threads:
+            t.join()
     srv.close()
+    assert not errors, errors
     assert len(set(tickets)) == len(jobs) and len(results) == len(jobs)
+    order = {0: 0, 1: 1, 2: 2, "gone": 3}
+    for t, states in seen.items():
+        ranks = [order[x] for x in states]
+        assert ranks == sorted(ranks) and 3 not in states, (t, states)
     for t, (w, steps) in zip(tickets, jobs):
         ca, ua, pa = _alone(w, steps)
         c, u, p, _, _ = results[t]
