@@ -81,6 +81,17 @@ __device__ __forceinline__ int wrap_i(int a, int n) {
 template <int N, typename Real, int TY>
 __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
   constexpr int M = N - 1;
+  // FP64 at N = 4 on 8-row tiles: the LDS rings (163 200 B) leave room for
+  // one 8-wave workgroup per CU, two waves per SIMD, if the registers fit in
+  // 256.  To get there this variant keeps fewer values live: each phase's
+  // previous phi is loaded with its CH pulls, the collision re-reads phi_i
+  // and C_i from LDS rather than holding them, the chemical-potential
+  // stencil is one inline copy, and the next plane's phi values are loaded
+  // after the collision rather than held through it.  Three moving spheres
+  // at 192^3: 2.04 ms (45.0% of the HBM roofline) against 2.26 ms (40.7%)
+  // on 4-row tiles at one wave per SIMD.  The same changes measured slower
+  // on every other variant (up to 9%), which keep the plain code.
+  constexpr bool kLean = sizeof(Real) == 8 && N == 4 && TY == 8;
   const NPL_CONST TileDesc3 *tp = (const NPL_CONST TileDesc3 *)a.strips + blockIdx.x;
   const int dom = tp->dom;
   if (dom < 0) return;
@@ -212,6 +223,9 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
 #pragma unroll
       for (int k = 0; k < 15; ++k) C.h[i][k] = pull(P, ybh, k, i * 15, kWall);
     });
+    if constexpr (kLean)
+      C.hi[i] = bld<Real>(row_rsrc(pvs, plp, phys_plane(plane_of(m))), xcu,
+                          ybp + (uint32_t)i * pb);
   };
   // NS populations (planes k - 1), stored previous phi and u
   auto pull_ns = [&](int m, Col3<M, Real> &C) {
@@ -222,8 +236,9 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
       for (int k = 1; k < 15; ++k) C.g[k] = pull(P, ybg, k, -1, kWall);
     });
     const Rsrc rp = row_rsrc(pvs, plp, zp);
+    if constexpr (!kLean)
 #pragma unroll
-    for (int i = 0; i < M; ++i) C.hi[i] = bld<Real>(rp, xcu, ybp + (uint32_t)i * pb);
+      for (int i = 0; i < M; ++i) C.hi[i] = bld<Real>(rp, xcu, ybp + (uint32_t)i * pb);
 #pragma unroll
     for (int d = 0; d < 3; ++d) C.pu[d] = bld<Real>(rp, xcu, ybp + (uint32_t)(M + d) * pb);
   };
@@ -279,6 +294,7 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
   // lane + 1 and, for the last two, 65 + lane.  Planes beyond a wall are
   // skipped: the collision next to the wall reads its own plane for the
   // mirror ghost.
+  constexpr bool kOneCopy = N >= 5 || kLean;
   auto chem_at = [&](int q, int c, int s0, int sU, int sD, int sc) {
     const int ty = q + 1;  // phi ring row of C ring row q
     Real phi[M], lap[M];
@@ -322,7 +338,7 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
   // out of line, and the call and its stack frame cost 16% of the step
   // (256^3 FP32: 3.56 against 3.00 ms).  Smaller N inline three copies.
   auto chem_row = [&](int q, int s0, int sU, int sD, int sc) __attribute__((always_inline)) {
-    if constexpr (N >= 5) {
+    if constexpr (kOneCopy) {
 #pragma unroll 1
       for (int pass = 0; pass < 2; ++pass) {
         const int c = pass == 0 ? lane + 1 : 65 + lane;
@@ -339,7 +355,7 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
       if (z < 0 || z >= nz) return;
     }
     const int s0 = ring5(mB), sU = ring5(mB + dir), sD = ring5(mB - dir), sc = ring4(mB);
-    if constexpr (N >= 5) {
+    if constexpr (kOneCopy) {
       // this wave's C rows: its own while it has one, and a halo row for
       // waves 0 and 1 (uniform over the wave)
       const int qa = ty <= nyi ? cr : -1;
@@ -474,18 +490,25 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
     }
 #pragma unroll
     for (int i = 0; i < M; ++i) {
+      Real phii = phi[i], Cvi = Cv[i];
       if constexpr (decltype(kLate)::value) {
         asm volatile("" ::: "memory");
         pull_phase(mC, i, P);
+        // plane mC's slots of the phi and C rings are rewritten only two
+        // iterations later, so these are the values read above
+        if constexpr (kLean) {
+          phii = sphi[s0][i][pr][ln];
+          Cvi = sC[c0][i][cr][ln];
+        }
       }
       const Real pp = P.hi[i];
       Real ps[3], dd[3];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        ps[d] = phi[i] * u[d];
+        ps[d] = phii * u[d];
         dd[d] = ps[d] - pp * P.pu[d];  // eq:N27
       }
-      const Real ec = K.eta_i[i] * Cv[i];
+      const Real ec = K.eta_i[i] * Cvi;
       const Real it = K.itau_i[i], sr = K.src_i[i];
       // eq:N24 with h^eq (eq:N25) and R_k (eq:N26) split into the parts
       // even and odd in c_k, per pair of opposite directions
@@ -512,10 +535,10 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
       Real lo = P.h[i][0];
 #pragma unroll
       for (int k = 1; k < 15; ++k) lo += P.h[i][k];
-      const Real bb = phi[i] - pp;
-      const Real err = (pp - (phi[i] - bb)) + (lo - bb);
+      const Real bb = phii - pp;
+      const Real err = (pp - (phii - bb)) + (lo - bb);
       bst<Real>(wh, xcu, ybh[1] + (uint32_t)(i * 15) * pb, err - hsum);
-      bst<Real>(wp, xcu, ybp + (uint32_t)i * pb, phi[i]);
+      bst<Real>(wp, xcu, ybp + (uint32_t)i * pb, phii);
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) bst<Real>(wp, xcu, ybp + (uint32_t)(M + d) * pb, u[d]);
@@ -539,11 +562,12 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
     if constexpr (kEarly)
       if (collide) pull_col(mC, col);
     stageA(mA, fr);
-    load_phi(mA + 1, fr);
+    if constexpr (!kLean) load_phi(mA + 1, fr);
     __syncthreads();
     stageB(mA - 1);
     __syncthreads();
     if (collide) stageC(mC, col, std::integral_constant<bool, !kEarly>());
+    if constexpr (kLean) load_phi(mA + 1, fr);
   }
 }
 
@@ -662,7 +686,8 @@ int occ3(int precision) {
 // Interior rows of a tile = waves of a workgroup: 4 in FP32, where two or
 // more 4-row workgroups per CU measured faster than one of 8 (256^3: N = 3
 // 48.3% against 44.9% of the HBM roofline, N = 5 38.2% against 35.6%); in
-// FP64 8 for N <= 3 (44.9% against 43.9% at N = 3) and 4 for N >= 4, where
+// FP64 8 for N <= 4 (N = 3: 44.9% against 43.9%; N = 4, with the leaner
+// register use of that variant: 45.0% against 40.7%) and 4 for N = 5, where
 // FP64 rings of 8 rows would not fit in LDS.  NPLBM_TY3 = 4 or 8 overrides.
 int step3_ty(int N, int precision) {
   if (const char *e = std::getenv("NPLBM_TY3")) {
@@ -671,7 +696,7 @@ int step3_ty(int N, int precision) {
     const int lds = (k3PR * (t + 4) + k3CR * (t + 2)) * (N - 1) * k3L * bytes;
     if (t == 4 || (t == 8 && lds <= 160 * 1024)) return t;
   }
-  return precision == 64 && N <= 3 ? 8 : 4;
+  return precision == 64 && N <= 4 ? 8 : 4;
 }
 
 hipError_t launch_step3(int N, int precision, int ty, const StepArgs &a, int nblocks, int nx,

@@ -47,13 +47,13 @@ def test_3d_tiny_parity(n, wall):
     assert max(_parity(w, 25)) < TOL
 
 
-@pytest.mark.parametrize("N,ty,prec", [(2, "4", 64), (3, "4", 64), (4, "8", 64), (3, "8", 32),
+@pytest.mark.parametrize("N,ty,prec", [(2, "4", 64), (3, "4", 64), (4, "4", 64), (3, "8", 32),
                                        (5, "8", 32)])
 def test_3d_other_tile_height(N, ty, prec, monkeypatch):
     # the tile height the default does not pick (NPLBM_TY3, read when the
-    # domain is created): FP64 4 rows for N <= 3 and 8 for N = 4, against the
-    # oracle; FP32 8 rows against the default FP64 kernel (at N = 5 8-row
-    # FP64 rings do not fit in LDS)
+    # domain is created): FP64 4 rows for N <= 4, against the oracle; FP32
+    # 8 rows against the default FP64 kernel (at N = 5 8-row FP64 rings do
+    # not fit in LDS)
     w = W.random_smooth3d(N, 100, 30, 12, seed=560 + N, wall_z=True, accept=oracle_accepts)
     if prec == 64:
         monkeypatch.setenv("NPLBM_TY3", ty)
