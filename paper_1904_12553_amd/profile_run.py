@@ -7,7 +7,8 @@
 ``step`` runs the benchmark workload (N=5, 2048 x 2048, FP32, the same
 launch configuration as bench.py) for a few eager steps; ``step3d`` the
 D3Q15 workloads of the benchmark (256^3, N = 5 slabs and spheres or the
-N = 3 static sphere); ``copy`` runs the
+N = 3 static sphere) or, with ``--n3 4``, three moving spheres at 192^3;
+``copy`` runs the
 library's plain copy kernel over a buffer of known size, whose FETCH_SIZE /
 WRITE_SIZE readings calibrate the counters, and prints the copy bandwidth
 measured with HIP events.
@@ -25,7 +26,8 @@ if ROOT not in sys.path:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--what", choices=["step", "step3d", "copy"], default="step")
-    ap.add_argument("--n3", type=int, default=5, help="phases of the 3-D workload (3 or 5)")
+    ap.add_argument("--n3", type=int, default=5, choices=[3, 4, 5],
+                    help="phases of the 3-D workload")
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--side", type=int, default=2048)
     ap.add_argument("--precision", type=int, default=32)
@@ -55,8 +57,9 @@ def main():
         print(json.dumps({"copy_bytes": n, "ms": ms, "GBps_read_plus_write": 2 * n / ms / 1e6}))
         return
     if args.what == "step3d":
-        w = (W.slabs_and_spheres(256, accept=P.accepts) if args.n3 == 5
-             else W.static_sphere(256, R=64.0))
+        w = {5: lambda: W.slabs_and_spheres(256, accept=P.accepts),
+             4: lambda: W.droplet_collision3d(192, accept=P.accepts),
+             3: lambda: W.static_sphere(256, R=64.0)}[args.n3]()
     else:
         w = W.bands_and_droplets(args.side, accept=P.accepts)
     d = P.Domain(precision=args.precision, **w.params())
