@@ -101,8 +101,7 @@ class OracleSim:
     relaxation time ``tau_phi`` (scalars or N-1 values), interface width
     ``W`` (= 2 sqrt(2) eta), body-force acceleration ``(gx, gy)``.
     ``force_form`` 0 is the total-force distribution of eq:N20_1, 1 the one
-    of Remark 1 (Sec. 3.1) with F = -div(J~ u) + F_s + G; 2 is a planted
-    mistake of form 1 (indices of the divergence swapped) that only tests use.
+    of Remark 1 (Sec. 3.1) with F = -div(J~ u) + F_s + G.
     """
 
     def __init__(self, N, nx, ny, sigma, rho, mu, mobility=0.1, tau_phi=0.8,

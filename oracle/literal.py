@@ -174,16 +174,13 @@ class LiteralSim:
         coef = (1 - self.N * self.gam[:-1] / self.Gam) * self.a * self.m
         J = -np.einsum("i,idyx->dyx", coef, gC)
         if self.force_form == 1:
-            # Remark 1: F -= div(J~ u_prev), (div)_a = sum_b d_b (J~_b u_a)
-            for a in range(2):
-                F[a] -= sum(self.grad(J[b] * self.pu[a])[b] for b in range(2))
+            F -= self.flux_divergence(J, self.pu)
         mom = np.einsum("kd,kyx->dyx", C.astype(float), self.g)
         u = (mom + 0.5 * F) / rho                                # eq:N22_1
         uu = u[0] ** 2 + u[1] ** 2
         s0 = WGT[0] * (-uu / (2 * CS2))
         p = CS2 / (1 - WGT[0]) * (self.g[1:].sum(axis=0) + 0.5 * (u * grho).sum(axis=0) + rho * s0)
-        mu = np.einsum("k,kyx->yx", self.mt, c)
-        taug = 0.5 + mu / (rho * CS2)
+        taug = self.tau_g(c, rho)
         return dict(phi=phi, c=c, rho=rho, C=Cp, F=F, J=J, grho=grho, u=u, p=p, taug=taug)
 
     def step(self, n=1):
@@ -208,7 +205,7 @@ class LiteralSim:
                                con / (2 * CS2 ** 2))
                 gs[k] = self.g[k] - (self.g[k] - geq[k]) / tg + (1 - 1 / (2 * tg)) * Gk
             heq = self.heq(m["phi"], m["C"], u)
-            dpu = m["phi"][:, None] * u[None] - self.pphi[:, None] * self.pu[None]   # eq:N27
+            dpu = self.flux_rate(m["phi"], u)
             hs = np.empty_like(self.h)
             for k in range(9):
                 R = ((1 - 1 / (2 * self.tau))[:, None, None] * WGT[k] *
@@ -217,6 +214,22 @@ class LiteralSim:
             self.pphi, self.pu = m["phi"].copy(), u.copy()
             self.h = self._stream(hs)
             self.g = self._stream(gs[None])[0]
+
+    # The three pieces below are separate methods so that a test can swap in
+    # a deliberately wrong reading and show that the pins reject it.
+    def flux_rate(self, phi, u):
+        """eq:N27: backward-Euler d_t(phi_i u) = phi_i u - phi_i(prev) u(prev),
+        shape (N-1, 2, ny, nx)."""
+        return phi[:, None] * u[None] - self.pphi[:, None] * self.pu[None]
+
+    def tau_g(self, c, rho):
+        """eq:N21_1 with the local dynamic viscosity mu = sum_k mu~_k c_k."""
+        mu = np.einsum("k,kyx->yx", self.mt, c)
+        return 0.5 + mu / (rho * CS2)
+
+    def flux_divergence(self, J, u):
+        """Remark 1: component a of div(J~ u) is sum_b d_b (J~_b u_a)."""
+        return np.stack([sum(self.grad(J[b] * u[a])[b] for b in range(2)) for a in range(2)])
 
     def _stream(self, fs):
         out = np.empty_like(fs)

@@ -221,8 +221,7 @@ static double g_eq(const orc_sim *s, int k, double rho, double p, double ux,
 /* eq:N20_1, contracted as written: (c c - cs^2 I) : T / (2 cs^4) with
    T = uF + Fu + cs^2 (u grad rho + grad rho u) + J u / (tau_g - 1/2).
    form 1: the distribution of Remark 1 (Sec. 3.1), the same without the
-   J u / (tau_g - 1/2) term (F then carries -div(J u)); form 2 is form 1
-   with a planted mistake (see macroscopic). */
+   J u / (tau_g - 1/2) term (F then carries -div(J u)). */
 static double G_force(int form, int k, double ux, double uy, double Fx, double Fy,
                       double rx, double ry, double Jx, double Jy,
                       double taug) {
@@ -233,7 +232,7 @@ static double G_force(int form, int k, double ux, double uy, double Fx, double F
     for (int b = 0; b < 2; ++b)
       T[a][b] = u[a] * F[b] + F[a] * u[b] + CS2 * u[a] * r[b] +
                 CS2 * r[a] * u[b] +
-                (form != 0 ? 0.0 : J[a] * u[b] / (1.0 * (taug - 0.5)));
+                (form == 1 ? 0.0 : J[a] * u[b] / (1.0 * (taug - 0.5)));
   double contr = 0.0;
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b)
@@ -360,7 +359,7 @@ int orc_create(int N, int nx, int ny, int wall_y, int grad_scheme,
   *out = NULL;
   if (N < 2 || N > NMAX || nx < 4 || ny < 4 || !(W > 0.0)) return ORC_EINVAL;
   if (grad_scheme != 0 && grad_scheme != 1) return ORC_EINVAL;
-  if (force_form < 0 || force_form > 2) return ORC_EINVAL;
+  if (force_form != 0 && force_form != 1) return ORC_EINVAL;
   orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));
   if (!s) return ORC_ENOMEM;
   s->N = N; s->nx = nx; s->ny = ny; s->wall_y = wall_y ? 1 : 0;
@@ -518,16 +517,12 @@ static void macroscopic(orc_sim *s) {
   }
   /* Remark 1 (Sec. 3.1): F = -div(J~ u) + F_s + G, component a of the
      divergence being sum_b d_b (J~_b u_a), with the previous step's u */
-  if (s->force_form != 0) {
-    /* force_form 2 is a PLANTED MISTAKE for the tests only: the divergence
-       taken over the other index, sum_b d_b (J~_a u_b), which a test must be
-       able to tell apart from the correct form */
-    const int swap = s->force_form == 2;
+  if (s->force_form == 1) {
     for (size_t x = 0; x < n; ++x) {
-      s->q[x] = s->J[x] * s->pu[x];                    /* J_x u_x */
-      s->q[n + x] = swap ? s->J[x] * s->pu[n + x] : s->J[n + x] * s->pu[x]; /* J_y u_x */
-      s->q[2 * n + x] = swap ? s->J[n + x] * s->pu[x] : s->J[x] * s->pu[n + x]; /* J_x u_y */
-      s->q[3 * n + x] = s->J[n + x] * s->pu[n + x];    /* J_y u_y */
+      s->q[x] = s->J[x] * s->pu[x];                  /* J_x u_x */
+      s->q[n + x] = s->J[n + x] * s->pu[x];          /* J_y u_x */
+      s->q[2 * n + x] = s->J[x] * s->pu[n + x];      /* J_x u_y */
+      s->q[3 * n + x] = s->J[n + x] * s->pu[n + x];  /* J_y u_y */
     }
     #pragma omp parallel for schedule(static) if (s->nx * s->ny >= 8192)
     for (int y = 0; y < ny; ++y)

@@ -3,8 +3,10 @@ G_k without the J~ u / (tau_g - 1/2) tensor term and F = -div(J~ u) + F_s + G,
 component a of the divergence being sum_b d_b (J~_b u_a) (the identity
 J~ . grad u = div(J~ u) - (div J~) u of Sec. 2 fixes the index order).
 
-force_form=2 is a planted mistake in the oracle (the divergence taken over
-the other index); the tests below must tell it apart from form 1.
+The planted mistake lives here, on the test side: ``SwappedDivergence`` is
+the NumPy transcription with the divergence taken over the other index,
+sum_b d_b (J~_a u_b).  The tests below must tell it apart from form 1; the
+oracle itself accepts force_form 0 and 1 only.
 """
 import numpy as np
 import pytest
@@ -15,6 +17,15 @@ from oracle.accept import oracle_accepts
 from oracle.literal import LiteralSim
 
 CS2 = 1.0 / 3.0
+
+
+class SwappedDivergence(LiteralSim):
+    """PLANTED MISTAKE (tests only): Remark 1's divergence over the wrong index."""
+
+    def flux_divergence(self, J, u):
+        return np.stack([sum(self.grad(J[a] * u[b])[b] for b in range(2)) for a in range(2)])
+
+
 CK = np.array([[0, 0], [1, 0], [0, 1], [-1, 0], [0, -1], [1, 1], [-1, 1], [-1, -1], [1, -1]], float)
 
 
@@ -56,8 +67,8 @@ def test_forms_identical_when_flux_vanishes(wall):
 
 
 @pytest.mark.parametrize("wall", [False, True])
-@pytest.mark.parametrize("ff", [1, 2])
-def test_divergence_of_flux_times_uniform_velocity(wall, ff):
+@pytest.mark.parametrize("planted", [False, True])
+def test_divergence_of_flux_times_uniform_velocity(wall, planted):
     """With the previous velocity uniform (u = U at t = 0), div(J~ U) is U
     times div J~ by linearity of the stencil: F(form 1) - F(eq:N20_1 form) =
     -U (div J~), with div J~ from the oracle's eq:N31a stencil applied to the
@@ -66,24 +77,29 @@ def test_divergence_of_flux_times_uniform_velocity(wall, ff):
     w = W.random_smooth(3, nx, ny, seed=72, wall_y=wall, accept=oracle_accepts)
     U = np.array([0.013, -0.021])
     u = np.broadcast_to(U[:, None, None], (2, ny, nx)).copy()
-    F = {}
-    for form in (0, ff):
-        s = OracleSim(**w.params(), force_form=form)
-        s.init(w.c, u)
-        f = s.fields()
-        F[form] = f["F"]
-        J = f["J"]
-    _, gJx = s.stencils(J[0])
-    _, gJy = s.stencils(J[1])
+    s0 = OracleSim(**w.params(), force_form=0)
+    s0.init(w.c, u)
+    f0 = s0.fields()
+    if planted:
+        s1 = SwappedDivergence(**w.params(), force_form=1)
+        s1.init(w.c, u)
+        F1 = s1.macro_all()["F"]
+    else:
+        s1 = OracleSim(**w.params(), force_form=1)
+        s1.init(w.c, u)
+        F1 = s1.fields()["F"]
+    J = f0["J"]
+    _, gJx = s0.stencils(J[0])
+    _, gJy = s0.stencils(J[1])
     divJ = gJx[0] + gJy[1]
     exp = -U[:, None, None] * divJ[None]
-    got = F[ff] - F[0]
+    got = F1 - f0["F"]
     assert np.max(np.abs(divJ)) > 1e-7
     err = np.max(np.abs(got - exp)) / np.max(np.abs(exp))
-    if ff == 1:
-        assert err < 1e-9
-    else:
+    if planted:
         assert err > 0.1
+    else:
+        assert err < 1e-9
 
 
 @pytest.mark.parametrize("N", [2, 3, 5])
@@ -122,8 +138,10 @@ def test_eq_N20_1_carries_the_symmetric_half_of_the_flux_term():
     rho = np.array([10.0, 1.0])
     uy = {}
     for ff in (0, 1, 2):
-        s = OracleSim(2, nx, ny, W.uniform_sigma(2, 1e-3), rho, 0.1 * rho, W=Wd,
-                      force_form=ff)
+        # 2 = the planted swapped-index form (test side)
+        cls = SwappedDivergence if ff == 2 else OracleSim
+        s = cls(2, nx, ny, W.uniform_sigma(2, 1e-3), rho, 0.1 * rho, W=Wd,
+                force_form=min(ff, 1))
         s.init(c, u)
         s.step(50)
         uy[ff] = s.macro()[1][1]
