@@ -262,14 +262,26 @@ int nplbm_poll(nplbm_server *s, uint64_t ticket, int32_t *state);
 
 /* Results of a finished request (host arrays of N, 2 and 1 fields, any may
  * be NULL) and its timing: seconds from submit to admission and from submit
- * to completion.  The request is forgotten afterwards. */
+ * to completion.  The request is forgotten afterwards.  A failed request
+ * (state 3: its admission or read-back raised an error) is forgotten too,
+ * and the call returns that error with its message.  NPLBM_ESTATE (the
+ * ticket stays valid) while the request is queued or resident;
+ * NPLBM_ENOTFOUND for an unknown or already collected ticket. */
 int nplbm_result(nplbm_server *s, uint64_t ticket, double *c, double *u,
                  double *p, double *admit_s, double *done_s);
 
-/* Aggregate statistics since creation: node-updates done and the busy
- * seconds of the pump loop. */
-int nplbm_server_stats(nplbm_server *s, double *node_updates, double *busy_s,
-                       int64_t *completed);
+/* Aggregate statistics since creation (any output may be NULL):
+ *   p50_s, p99_s  median and 99th percentile of the time from nplbm_submit
+ *                 to completion over every request completed so far
+ *                 (linear interpolation between order statistics; 0 if
+ *                 none);
+ *   mlups         node updates done / (last completion - first submission)
+ *                 / 1e6: aggregate throughput of the whole stream;
+ *   node_updates  node updates done, busy_s seconds spent inside
+ *                 nplbm_server_pump, completed requests finished.
+ * Thread-safe. */
+int nplbm_server_stats(nplbm_server *s, double *p50_s, double *p99_s, double *mlups,
+                       double *node_updates, double *busy_s, int64_t *completed);
 
 void nplbm_server_destroy(nplbm_server *s);
 

@@ -356,14 +356,14 @@ __global__ void k_diag_partial(const double *c, int N, int64_t n, double *partia
   }
 }
 
-__global__ void k_diag_final(const double *partials, int nq, int nblk, const int *ismax,
-                             double *out) {
+// entry qmax of each partial record is a maximum, the others are sums
+__global__ void k_diag_final(const double *partials, int nq, int nblk, int qmax, double *out) {
   const int q = threadIdx.x;
   if (q >= nq) return;
   double r = 0.0;
   for (int b = 0; b < nblk; ++b) {
     const double v = partials[(int64_t)b * nq + q];
-    r = ismax[q] ? fmax(r, v) : r + v;
+    r = q == qmax ? fmax(r, v) : r + v;
   }
   out[q] = r;
 }
@@ -420,8 +420,6 @@ __global__ void k_copy1(unsigned char *dst, const unsigned char *src, int64_t n)
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = src[i];
 }
-
-__constant__ int c_diag_ismax[kMaxN + 2];
 
 }  // namespace
 
@@ -491,16 +489,8 @@ int diag_blocks(int64_t n) {
 
 hipError_t launch_diag(const double *c, int N, int64_t n, double *partials, int nblk,
                        double *out, hipStream_t st) {
-  int ismax[kMaxN + 2] = {0};
-  ismax[N] = 1;
-  hipError_t e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_diag_ismax), ismax, sizeof(ismax), 0,
-                                        hipMemcpyHostToDevice, st);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_diag_partial, dim3(nblk), dim3(kThreads), 0, st, c, N, n, partials);
-  int *dismax = nullptr;
-  e = hipGetSymbolAddress((void **)&dismax, HIP_SYMBOL(c_diag_ismax));
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, st, partials, N + 2, nblk, dismax, out);
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, st, partials, N + 2, nblk, N, out);
   return hipGetLastError();
 }
 

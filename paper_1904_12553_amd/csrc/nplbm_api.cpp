@@ -32,14 +32,15 @@ struct nplbm_domain {
   int ty = 8;                // tile rows of the 3-D step kernel
   int64_t t = 0;
   bool initialised = false;
-  // graph of kGraphSteps consecutive steps starting from an even time
-  hipGraphExec_t graph = nullptr;
-  int graph_steps = 0;
+  // graphs of 2^j consecutive steps (j = 0..kGraphLevels-1) starting at an
+  // even (index 0) or odd (index 1) time step
+  hipGraphExec_t graph[2][7] = {{nullptr}};
 };
 
 namespace {
 
-constexpr int kGraphSteps = 64;
+// step runs are replayed as graphs of 64, 32, ..., 1 steps
+constexpr int kGraphLevels = 7;
 
 double *dptr(nplbm_domain *d, size_t off) { return reinterpret_cast<double *>(d->base + off); }
 
@@ -75,9 +76,10 @@ int launch_one_step(nplbm_domain *d) {
   return NPLBM_OK;
 }
 
-int capture_graph(nplbm_domain *d) {
-  if (d->graph) return NPLBM_OK;
-  if (!d->stream) return NPLBM_OK;  // the null stream cannot be captured
+// Capture (once) the graph of 2^level steps starting at a time of parity
+// `par`: the launches alternate the ping-pong buffers from that parity.
+int capture_graph(nplbm_domain *d, int par, int level) {
+  if (d->graph[par][level]) return NPLBM_OK;
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamBeginCapture(d->stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
@@ -86,8 +88,8 @@ int capture_graph(nplbm_domain *d) {
   a.strips = d->strips_dev;
   a.doms = d->desc_dev;
   hipError_t le = hipSuccess;
-  for (int s = 0; s < kGraphSteps && le == hipSuccess; ++s) {
-    a.substep = s & 1;
+  for (int s = 0; s < (1 << level) && le == hipSuccess; ++s) {
+    a.substep = (par + s) & 1;
     le = launch_any_step(d, a);
   }
   e = hipStreamEndCapture(d->stream, &g);
@@ -96,14 +98,24 @@ int capture_graph(nplbm_domain *d) {
     return hip_fail(le, "step launch during capture");
   }
   if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-  e = hipGraphInstantiate(&d->graph, g, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(&d->graph[par][level], g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) {
-    d->graph = nullptr;
+    d->graph[par][level] = nullptr;
     return hip_fail(e, "hipGraphInstantiate");
   }
-  d->graph_steps = kGraphSteps;
   return NPLBM_OK;
+}
+
+// The graphs a run starting at an even time uses, and the one-step graph
+// of odd start: captured together at the first step call, so that later
+// runs of any length replay existing graphs.
+int capture_all(nplbm_domain *d) {
+  for (int level = 0; level < kGraphLevels; ++level) {
+    int rc = capture_graph(d, 0, level);
+    if (rc) return rc;
+  }
+  return capture_graph(d, 1, 0);
 }
 
 int readback(nplbm_domain *d, bool want_up) {
@@ -314,22 +326,31 @@ int nplbm_step(nplbm_domain *d, int64_t nsteps) {
   if (!check_domain(d)) return fail(NPLBM_EINVAL, "NULL domain");
   if (nsteps < 0) return fail(NPLBM_EINVAL, "nsteps < 0");
   if (!d->initialised) return fail(NPLBM_ESTATE, "nplbm_set_fields was not called");
-  const bool use_graph = std::getenv("NPLBM_NO_GRAPH") == nullptr;
+  // runs are replayed as HIP graphs of 2^j steps (the largest that fits the
+  // steps left, at most 64); the null stream cannot be captured, so there
+  // (and with NPLBM_NO_GRAPH set) every step is launched on its own
+  const bool use_graph = d->stream && std::getenv("NPLBM_NO_GRAPH") == nullptr;
+  if (use_graph && nsteps > 0) {
+    int rc = capture_all(d);
+    if (rc) return rc;
+  }
   while (nsteps > 0) {
-    if (use_graph && d->stream && (d->t & 1) == 0 && nsteps >= kGraphSteps) {
-      int rc = capture_graph(d);
-      if (rc) return rc;
-    }
-    if (d->graph && (d->t & 1) == 0 && nsteps >= d->graph_steps) {
-      hipError_t e = hipGraphLaunch(d->graph, d->stream);
-      if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
-      d->t += d->graph_steps;
-      nsteps -= d->graph_steps;
-    } else {
+    if (!use_graph) {
       int rc = launch_one_step(d);
       if (rc) return rc;
       nsteps -= 1;
+      continue;
     }
+    int level = kGraphLevels - 1;
+    while ((int64_t)1 << level > nsteps) --level;
+    const int par = (int)(d->t & 1);
+    if (par) level = 0;  // an odd start takes one step to reach even parity
+    int rc = capture_graph(d, par, level);
+    if (rc) return rc;
+    hipError_t e = hipGraphLaunch(d->graph[par][level], d->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    d->t += (int64_t)1 << level;
+    nsteps -= (int64_t)1 << level;
   }
   return NPLBM_OK;
 }
@@ -427,7 +448,9 @@ void nplbm_destroy(nplbm_domain *d) {
   if (!d) return;
   if (d->stream) (void)hipStreamSynchronize(d->stream);
   else (void)hipDeviceSynchronize();
-  if (d->graph) (void)hipGraphExecDestroy(d->graph);
+  for (auto &row : d->graph)
+    for (hipGraphExec_t &g : row)
+      if (g) (void)hipGraphExecDestroy(g);
   if (d->own_mem && d->base) (void)hipFree(d->base);
   delete d;
 }

@@ -20,6 +20,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "host_internal.h"
@@ -49,6 +50,8 @@ struct Req {
   // 0 queued, 1 resident, 2 done, 3 failed; written and read only under the
   // server's mutex, after everything it publishes (results, times) is written
   int state = 0;
+  int err = 0;      // failed request: the error code and message
+  std::string msg;
   double t_submit = 0, t_admit = 0, t_done = 0;
   // resident
   Derived d;
@@ -89,6 +92,10 @@ struct nplbm_server {
   bool dirty = true;
   double node_updates = 0, busy = 0;
   int64_t completed = 0;
+  // completion latencies (submit to done) of every finished request, and
+  // the first submission / last completion times (under the mutex)
+  std::vector<double> lat;
+  double t_first = -1.0, t_last = 0.0;
 };
 
 namespace {
@@ -188,8 +195,12 @@ int rebuild(nplbm_server *s) {
         s->groups.push_back({N, prec, sch, all.size(), g.size()});
         all.insert(all.end(), g.begin(), g.end());
       }
-  s->dirty = false;
-  if (all.empty()) return NPLBM_OK;
+  // the resident set is marked clean only once its graph exists: a failed
+  // rebuild leaves it dirty, so the next pump tries again
+  if (all.empty()) {
+    s->dirty = false;
+    return NPLBM_OK;
+  }
   if (all.size() > s->strips_cap) {
     if (s->strips_dev) (void)hipFree(s->strips_dev);
     s->strips_dev = nullptr;
@@ -265,7 +276,24 @@ int rebuild(nplbm_server *s) {
     s->graph = nullptr;
     return hip_fail(e, "hipGraphInstantiate");
   }
+  s->dirty = false;
   return NPLBM_OK;
+}
+
+// Publish the outcome of a request (under the mutex): done, with its
+// latency recorded, or failed, with the error the admission or read-back
+// raised.
+void finish(nplbm_server *s, Req *r, int rc) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (rc) {
+    r->err = rc;
+    r->msg = last_error();
+    r->state = 3;
+    return;
+  }
+  s->lat.push_back(r->t_done - r->t_submit);
+  s->t_last = std::max(s->t_last, r->t_done);
+  r->state = 2;
 }
 
 int retire(nplbm_server *s, Req *r) {
@@ -372,6 +400,7 @@ int nplbm_submit(nplbm_server *s, const nplbm_params *p, const double *c, const 
   r->nsteps = nsteps;
   r->t_submit = now_s();
   std::lock_guard<std::mutex> lk(s->mu);
+  if (s->t_first < 0.0) s->t_first = r->t_submit;
   r->ticket = s->next_ticket++;
   s->reqs[r->ticket] = r;
   s->queue.push_back(r);
@@ -394,22 +423,21 @@ int nplbm_server_pump(nplbm_server *s, int32_t *active_out) {
   for (Req *r : cand) {
     if (nres >= s->max_slots) break;
     if (s->used + r->bytes > s->budget) continue;
-    const int rc = admit(s, r);
-    int state = rc ? 3 : 1;
-    if (!rc && r->nsteps == 0)
-      state = retire(s, r) ? 3 : 2;
-    else if (!rc)
-      ++nres;
+    int rc = admit(s, r);
     {
       std::lock_guard<std::mutex> lk(s->mu);
       s->queue.erase(std::find(s->queue.begin(), s->queue.end(), r));
-      r->state = state;
+      if (!rc) r->state = 1;
     }
+    if (!rc && r->nsteps == 0) rc = retire(s, r);
+    else if (!rc) ++nres;
+    if (rc || r->nsteps == 0) finish(s, r, rc);
   }
   if (s->dirty) {
     int rc = rebuild(s);
     if (rc) return rc;
   }
+  if (nres > 0 && !s->graph) return fail(NPLBM_ESTATE, "resident requests but no quantum graph");
   if (s->graph) {
     // per-domain progress for this quantum
     double nodes = 0;
@@ -435,11 +463,7 @@ int nplbm_server_pump(nplbm_server *s, int32_t *active_out) {
       Req *r = s->slots[slot];
       if (!r) continue;
       r->done_steps += std::min<int64_t>(s->quantum, r->nsteps - r->done_steps);
-      if (r->done_steps >= r->nsteps) {
-        const int state = retire(s, r) ? 3 : 2;
-        std::lock_guard<std::mutex> lk(s->mu);
-        r->state = state;
-      }
+      if (r->done_steps >= r->nsteps) finish(s, r, retire(s, r));
     }
   }
   if (active_out) {
@@ -471,6 +495,14 @@ int nplbm_result(nplbm_server *s, uint64_t ticket, double *c, double *u, double 
     auto it = s->reqs.find(ticket);
     if (it == s->reqs.end()) return fail(NPLBM_ENOTFOUND, "unknown ticket");
     r = it->second;
+    if (r->state == 3) {
+      // a failed request is reaped here: its error is returned once
+      s->reqs.erase(it);
+      const int err = r->err ? r->err : NPLBM_EDEVICE;
+      const std::string msg = r->msg;
+      delete r;
+      return fail(err, "request %llu failed: %s", (unsigned long long)ticket, msg.c_str());
+    }
     if (r->state != 2) return fail(NPLBM_ESTATE, "request not finished (state %d)", r->state);
     s->reqs.erase(it);
   }
@@ -483,10 +515,30 @@ int nplbm_result(nplbm_server *s, uint64_t ticket, double *c, double *u, double 
   return NPLBM_OK;
 }
 
-int nplbm_server_stats(nplbm_server *s, double *node_updates, double *busy_s,
-                       int64_t *completed) {
+int nplbm_server_stats(nplbm_server *s, double *p50_s, double *p99_s, double *mlups,
+                       double *node_updates, double *busy_s, int64_t *completed) {
   clear_error();
   if (!s) return fail(NPLBM_EINVAL, "NULL server");
+  std::vector<double> lat;
+  double span = 0.0;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    lat = s->lat;
+    span = s->t_first >= 0.0 ? s->t_last - s->t_first : 0.0;
+  }
+  // percentiles by linear interpolation between order statistics (rank
+  // q (n - 1) of the sorted latencies)
+  std::sort(lat.begin(), lat.end());
+  auto pct = [&](double q) {
+    if (lat.empty()) return 0.0;
+    const double pos = q * (double)(lat.size() - 1);
+    const size_t i = (size_t)pos;
+    const double f = pos - (double)i;
+    return i + 1 < lat.size() ? lat[i] + f * (lat[i + 1] - lat[i]) : lat[i];
+  };
+  if (p50_s) *p50_s = pct(0.50);
+  if (p99_s) *p99_s = pct(0.99);
+  if (mlups) *mlups = span > 0.0 ? s->node_updates / span / 1e6 : 0.0;
   if (node_updates) *node_updates = s->node_updates;
   if (busy_s) *busy_s = s->busy;
   if (completed) *completed = s->completed;

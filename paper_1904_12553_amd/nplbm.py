@@ -24,6 +24,8 @@ LIB_PATH = os.environ.get("NPLBM_LIB") or os.path.join(HERE, "libnplbm.so")
 NPLBM_OK = 0
 ERRORS = {-1: "EINVAL", -2: "ENOTSPD", -3: "ENOMEM", -4: "EDEVICE", -5: "ETOOBIG",
           -6: "ESTATE", -7: "ENOTFOUND"}
+# nplbm_result keeps the ticket only while the request is unfinished
+ERRORS_KEEP_TICKET = -6
 
 # every symbol declared in include/nplbm.h
 EXPORTS = [
@@ -101,7 +103,7 @@ def lib():
             "nplbm_server_pump": ([vp, ctypes.POINTER(c_i32)], c_int),
             "nplbm_poll": ([vp, c_u64, ctypes.POINTER(c_i32)], c_int),
             "nplbm_result": ([vp, c_u64, dp, dp, dp, dp, dp], c_int),
-            "nplbm_server_stats": ([vp, dp, dp, ctypes.POINTER(c_i64)], c_int),
+            "nplbm_server_stats": ([vp, dp, dp, dp, dp, dp, ctypes.POINTER(c_i64)], c_int),
             "nplbm_server_destroy": ([vp], None),
         }
         for name, (args, res) in sig.items():
@@ -177,8 +179,10 @@ class Domain:
     """One lattice domain on the GPU.
 
     Keyword arguments are those of ``make_params``.  Device memory is a
-    torch uint8 tensor on ``device`` handed to the library; all launches go
-    to torch's current stream on that device (or ``stream``).
+    torch uint8 tensor on ``device`` handed to the library.  All launches go
+    to ``stream`` (a torch stream), by default a stream of the domain's own
+    (default priority): step runs are replayed as HIP graphs, which the
+    null stream (torch's default) cannot capture.
     """
 
     def __init__(self, device: str = "cuda:0", stream=None, **kw):
@@ -194,8 +198,10 @@ class Domain:
             _check(L.nplbm_validate(ctypes.byref(self._p), None, None, None))
         self.device = torch.device(device)
         with torch.cuda.device(self.device):
-            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
             self.mem = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            # the buffer is used on self.stream from here on
+            torch.cuda.current_stream(self.device).synchronize()
             ptr = self.mem.data_ptr()
             aligned = (ptr + 255) & ~255
             h = ctypes.c_void_p()
@@ -347,18 +353,27 @@ class Server:
         return s.value
 
     def result(self, ticket: int):
-        N, ny, nx = self._shapes.pop(ticket)
+        """(c, u, p, admit_s, done_s) of a finished request.  A failed
+        request raises its error (and is forgotten); a request still queued
+        or resident raises NPLBM_ESTATE and keeps its ticket."""
+        N, ny, nx = self._shapes[ticket]
         c = np.empty((N, ny, nx))
         u = np.empty((2, ny, nx))
         p = np.empty((ny, nx))
         a, d = ctypes.c_double(), ctypes.c_double()
-        _check(lib().nplbm_result(self._h, ctypes.c_uint64(ticket), _dp(c), _dp(u), _dp(p),
-                                  ctypes.byref(a), ctypes.byref(d)))
+        rc = lib().nplbm_result(self._h, ctypes.c_uint64(ticket), _dp(c), _dp(u), _dp(p),
+                                ctypes.byref(a), ctypes.byref(d))
+        if rc != ERRORS_KEEP_TICKET:
+            self._shapes.pop(ticket, None)
+        _check(rc)
         return c, u, p, a.value, d.value
 
-    def stats(self):
-        nu, busy = ctypes.c_double(), ctypes.c_double()
+    def stats(self) -> dict:
+        """Aggregate statistics of the server (include/nplbm.h)."""
+        p50, p99, ml, nu, busy = (ctypes.c_double() for _ in range(5))
         done = ctypes.c_int64()
-        _check(lib().nplbm_server_stats(self._h, ctypes.byref(nu), ctypes.byref(busy),
+        _check(lib().nplbm_server_stats(self._h, ctypes.byref(p50), ctypes.byref(p99),
+                                        ctypes.byref(ml), ctypes.byref(nu), ctypes.byref(busy),
                                         ctypes.byref(done)))
-        return nu.value, busy.value, done.value
+        return {"p50_s": p50.value, "p99_s": p99.value, "mlups": ml.value,
+                "node_updates": nu.value, "busy_s": busy.value, "completed": done.value}

@@ -3,12 +3,15 @@
     python3 -m paper_1904_12553_amd.profile_run --what step --steps 10
     python3 -m paper_1904_12553_amd.profile_run --what step3d --n3 5 --steps 10
     python3 -m paper_1904_12553_amd.profile_run --what copy --mib 1024
+    python3 -m paper_1904_12553_amd.profile_run --what sweep --n2 3 --steps 10
 
 ``step`` runs the benchmark workload (N=5, 2048 x 2048, FP32, the same
 launch configuration as bench.py) for a few eager steps; ``step3d`` the
 D3Q15 workloads of the benchmark (256^3, N = 5 slabs and spheres or the
 N = 3 static sphere) or, with ``--n3 4``, three moving spheres at 192^3;
-``copy`` runs the
+``sweep`` the other 2-D phase counts of the benchmark (``--n2 3``: the
+N = 3 static droplet at 4096^2, ``--n2 4``: the N = 4 droplet collision at
+3072^2); ``copy`` runs the
 library's plain copy kernel over a buffer of known size, whose FETCH_SIZE /
 WRITE_SIZE readings calibrate the counters, and prints the copy bandwidth
 measured with HIP events.
@@ -25,7 +28,9 @@ if ROOT not in sys.path:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--what", choices=["step", "step3d", "copy"], default="step")
+    ap.add_argument("--what", choices=["step", "step3d", "sweep", "copy"], default="step")
+    ap.add_argument("--n2", type=int, default=3, choices=[3, 4],
+                    help="phases of the 2-D sweep workload")
     ap.add_argument("--n3", type=int, default=5, choices=[3, 4, 5],
                     help="phases of the 3-D workload")
     ap.add_argument("--steps", type=int, default=10)
@@ -56,7 +61,10 @@ def main():
         ms = e0.elapsed_time(e1) / reps
         print(json.dumps({"copy_bytes": n, "ms": ms, "GBps_read_plus_write": 2 * n / ms / 1e6}))
         return
-    if args.what == "step3d":
+    if args.what == "sweep":
+        w = (W.static_droplet(4096, 4096, R=1000) if args.n2 == 3
+             else W.droplet_collision(3072, accept=P.accepts))
+    elif args.what == "step3d":
         w = {5: lambda: W.slabs_and_spheres(256, accept=P.accepts),
              4: lambda: W.droplet_collision3d(192, accept=P.accepts),
              3: lambda: W.static_sphere(256, R=64.0)}[args.n3]()

@@ -1,10 +1,12 @@
 """Serving: continuous batching of mixed-N, mixed-size domains gives the
 same result for every request as running it alone (bitwise, FP32), with
-requests admitted while others are resident and finishing mid-quantum."""
+requests admitted while others are resident and finishing mid-quantum, and
+every served FP64 request matches the FP64 oracle (1e-10 max-abs)."""
 import numpy as np
 import pytest
 
 import workloads as W
+from gpu_util import maxabs, oracle_run
 
 pytestmark = pytest.mark.gpu
 
@@ -46,9 +48,15 @@ def test_alone_equals_mix():
         ca, ua, pa = _alone(w, r.steps)
         assert np.array_equal(c, ca) and np.array_equal(u, ua) and np.array_equal(p, pa), r
         assert fin >= adm >= 0.0
-    nu, busy, done = srv.stats()
-    assert done == len(reqs)
-    assert nu == pytest.approx(sum(w.nx * w.ny * r.steps for r, w in zip(reqs, ws)))
+    st = srv.stats()
+    assert st["completed"] == len(reqs)
+    assert st["node_updates"] == pytest.approx(sum(w.nx * w.ny * r.steps for r, w in zip(reqs, ws)))
+    # the library's latency percentiles and throughput
+    lat = sorted(results[t][4] for t in tickets)
+    assert 0.0 < st["p50_s"] <= st["p99_s"] <= lat[-1] + 1e-9
+    assert st["p50_s"] == pytest.approx(float(np.percentile(lat, 50)), rel=1e-9)
+    assert st["p99_s"] == pytest.approx(float(np.percentile(lat, 99)), rel=1e-9)
+    assert st["mlups"] > 0.0
 
 
 def test_budget_admission_and_too_big():
@@ -60,6 +68,10 @@ def test_budget_admission_and_too_big():
     t2 = srv.submit(w.c, None, nsteps=30, precision=32, **w.params())
     srv.pump()
     assert srv.poll(t1) == 1 and srv.poll(t2) == 0   # only one fits the budget
+    # asking too early is an error that keeps the ticket
+    with pytest.raises(P.NplbmError) as e:
+        srv.result(t2)
+    assert e.value.code == -6 and srv.poll(t2) == 0
     big = W.static_droplet(128, 128, R=30, precision=32)
     with pytest.raises(P.NplbmError) as e:
         srv.submit(big.c, None, nsteps=10, precision=32, **big.params())
@@ -67,6 +79,65 @@ def test_budget_admission_and_too_big():
     for _ in range(20):
         srv.pump()
     assert srv.poll(t1) == 2 and srv.poll(t2) == 2
+    for t in (t1, t2):
+        c, _, _, _, _ = srv.result(t)
+        assert np.all(np.isfinite(c))
+    with pytest.raises(P.NplbmError) as e:           # collected once only
+        srv.result(t1)
+    assert e.value.code == -7
+
+
+def test_served_fp64_requests_match_the_oracle():
+    """FP64 requests of the three schemes, periodic and with walls, served in
+    a mix with FP32 requests: two are admitted into the running mix, most
+    finish in the middle of a quantum; each one's c, u and p match the FP64
+    oracle run of the same request within 1e-10 max-abs."""
+    import paper_1904_12553_amd as P
+    from oracle.accept import oracle_accepts
+    mk = lambda N, nx, ny, seed, wall: W.random_smooth(N, nx, ny, seed=seed, wall_y=wall,
+                                                       accept=oracle_accepts)
+    first = [(mk(3, 48, 40, 901, False), {}, 64, 70),
+             (mk(4, 40, 36, 902, True), {"grad_scheme": 1}, 64, 53),
+             (mk(2, 36, 30, 903, True), {"force_form": 1}, 64, 45),
+             (mk(5, 64, 64, 904, False), {}, 32, 100)]
+    later = [(mk(5, 44, 40, 905, True), {}, 64, 37),
+             (mk(3, 50, 30, 906, False), {"force_form": 1}, 64, 21),
+             (mk(4, 33, 20, 907, False), {"grad_scheme": 1}, 32, 29)]
+    print("case served FP64 vs oracle: " + ", ".join(
+        f"N={w.N} {w.nx}x{w.ny} {o} fp{p} {s}" for w, o, p, s in first + later), flush=True)
+    srv = P.Server(hbm_budget=1 << 31, max_slots=8, quantum=16)
+    tickets = {}
+    for job in first:
+        w, over, prec, steps = job
+        tickets[srv.submit(w.c, w.u, nsteps=steps, precision=prec,
+                           **dict(w.params(), **over))] = job
+    srv.pump()
+    srv.pump()                      # 32 steps into the first requests
+    for job in later:
+        w, over, prec, steps = job
+        tickets[srv.submit(w.c, w.u, nsteps=steps, precision=prec,
+                           **dict(w.params(), **over))] = job
+    results = {}
+    for _ in range(200):
+        srv.pump()
+        for t in tickets:
+            if t not in results and srv.poll(t) == 2:
+                results[t] = srv.result(t)
+        if len(results) == len(tickets):
+            break
+    srv.close()
+    assert len(results) == len(tickets)
+    checked = 0
+    for t, (w, over, prec, steps) in tickets.items():
+        if prec != 64:
+            continue
+        c, u, p, _, _ = results[t]
+        o = oracle_run(w, steps, **over)
+        oc, ou, op = o.macro()
+        err = max(maxabs(c, oc), maxabs(u, ou), maxabs(p, op))
+        assert err < 1e-10, (w.N, w.nx, w.ny, over, steps, err)
+        checked += 1
+    assert checked == 5
 
 
 def test_server_in_a_fresh_process_that_loads_the_library_first():
