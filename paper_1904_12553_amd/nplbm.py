@@ -356,6 +356,9 @@ class Server:
         """(c, u, p, admit_s, done_s) of a finished request.  A failed
         request raises its error (and is forgotten); a request still queued
         or resident raises NPLBM_ESTATE and keeps its ticket."""
+        if ticket not in self._shapes:   # unknown here: the library says why
+            _check(lib().nplbm_result(self._h, ctypes.c_uint64(ticket), None, None, None,
+                                      None, None))
         N, ny, nx = self._shapes[ticket]
         c = np.empty((N, ny, nx))
         u = np.empty((2, ny, nx))
