@@ -185,6 +185,28 @@ int nplbm_diagnostics(nplbm_domain *d, double *mass_out, double *max_sum_dev,
                       int64_t *nonfinite);
 
 /*
+ * For callers that cannot allocate device memory or synchronise (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the conservation diagnostics of nplbm_diagnostics, written to device
+ * memory and allocating nothing.
+ *   out_dev  caller-owned device buffer of N + 2 doubles: sum_x c_k for
+ *            k = 0..N-1, then max_x |sum_k c_k - 1|, then the number of
+ *            nodes with a non-finite c_k (as a double).
+ * Asynchronous on the domain's stream; enqueues kernels only (the FP64
+ * read-back into the domain's own read-back planes, then the reduction) and
+ * reads the state current at enqueue time.  The reduction's partial records
+ * live in a static device array of the library (1024 x 10 doubles + 16, about
+ * 82 KB, held on each GPU it runs on until the process ends) instead of the
+ * domain's allocation: every call on one GPU shares it, so calls that
+ * overlap on one GPU (other streams or threads) race.  Results equal
+ * nplbm_diagnostics' bitwise (same kernels, same block count).  Errors:
+ * NPLBM_EINVAL (NULL argument, the domain belongs to another device than
+ * the current one, or a reduction larger than the static array, which the
+ * 1024-block cap rules out), NPLBM_ESTATE, NPLBM_EDEVICE.
+ */
+int nplbm_diagnostics_noalloc(nplbm_domain *d, double *out_dev);
+
+/*
  * Laplace pressure jump of a droplet centred at (xc, yc) (Sec. 4.1): the
  * mean of p over nodes with distance <= r_in minus the mean over nodes with
  * distance >= r_out (plain Euclidean distance), reduced in FP64 on the GPU.

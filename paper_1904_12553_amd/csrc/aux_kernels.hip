@@ -3,6 +3,7 @@
 // None of these run inside the time loop except the diagnostics, which the
 // caller invokes every K steps.
 #include <algorithm>
+#include <mutex>
 
 #include "lattice.h"
 #include "nplbm_internal.h"
@@ -480,6 +481,39 @@ hipError_t launch_macro(const DomDesc *dd_dev, const DomDesc &dd, int precision,
     hipLaunchKernelGGL(k_macro_up<float>, dim3(nb), dim3(kThreads), 0, st, dd_dev, M, parity,
                        phi, rho, C, qq, u_out, p_out);
   return hipGetLastError();
+}
+
+// ---- the static scratch of nplbm_diagnostics_noalloc ----
+// Partial records of the diagnostics reduction (at most diag_blocks() = 1024
+// blocks of N + 2 doubles) followed by room for the final record, in a
+// file-scope device array so that the entry point allocates nothing.  Each
+// GPU holds its own copy until the process ends.  In host code `scratch`
+// names a host-side stand-in, not device memory: kernels and copies get the
+// per-device address hipGetSymbolAddress returns (static_diag_scratch).
+static __device__ __align__(256) double scratch[kStaticDiagDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {nullptr};
+}  // namespace
+
+hipError_t static_diag_scratch(double **out) {
+  *out = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    // once per device, with that device current
+    double *ptr = nullptr;
+    e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 int diag_blocks(int64_t n) {

@@ -201,6 +201,14 @@ int nplbm_create(const nplbm_params *p, void *stream, void *device_mem, size_t d
     delete d;
     return hip_fail(e, "hipGetDevice");
   }
+  // set-up of the static scratch of nplbm_diagnostics_noalloc on this device
+  // (its address is looked up once per device, here, outside any capture)
+  double *scr = nullptr;
+  e = static_diag_scratch(&scr);
+  if (e != hipSuccess) {
+    delete d;
+    return hip_fail(e, "static scratch address");
+  }
   d->stream = static_cast<hipStream_t>(stream);
   if (device_mem) {
     if (device_bytes < d->L.total) {
@@ -401,6 +409,31 @@ int nplbm_diagnostics(nplbm_domain *d, double *mass_out, double *max_sum_dev,
     for (int k = 0; k < N; ++k) mass_out[k] = out[k];
   if (max_sum_dev) *max_sum_dev = out[N];
   if (nonfinite) *nonfinite = (int64_t)out[N + 1];
+  return NPLBM_OK;
+}
+
+int nplbm_diagnostics_noalloc(nplbm_domain *d, double *out_dev) {
+  clear_error();
+  if (!check_domain(d) || !out_dev) return fail(NPLBM_EINVAL, "NULL argument");
+  if (!d->initialised) return fail(NPLBM_ESTATE, "nplbm_set_fields was not called");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != d->device)
+    return fail(NPLBM_EINVAL, "the domain lives on device %d, device %d is current", d->device,
+                dev);
+  const int N = d->p.N;
+  const int nblk = d->L.nblk;
+  if ((int64_t)nblk * (N + 2) > kStaticDiagPartials)
+    return fail(NPLBM_EINVAL, "reduction of %d blocks x %d values exceeds the static scratch "
+                "(%d doubles)", nblk, N + 2, kStaticDiagPartials);
+  double *scr = nullptr;
+  e = static_diag_scratch(&scr);
+  if (e != hipSuccess) return hip_fail(e, "static scratch address");
+  int rc = readback(d, false);
+  if (rc) return rc;
+  e = launch_diag(dptr(d, d->L.c), N, (int64_t)nnodes(d), scr, nblk, out_dev, d->stream);
+  if (e != hipSuccess) return hip_fail(e, "diag launch");
   return NPLBM_OK;
 }
 

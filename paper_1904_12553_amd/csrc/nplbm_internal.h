@@ -176,6 +176,14 @@ hipError_t launch_macro(const DomDesc *dd_dev, const DomDesc &dd, int precision,
 // FP64 reductions over the c fields (N planes): per-phase sums, max
 // |sum c - 1|, non-finite count.  partials must hold nblk*(N+2) doubles.
 int diag_blocks(int64_t n);
+// Doubles in the static device scratch of the allocation-free diagnostics:
+// the partial records of the most blocks diag_blocks() returns, plus the
+// final record, at the largest N.
+constexpr int kStaticDiagPartials = 1024 * (kMaxN + 2);
+constexpr int kStaticDiagDoubles = kStaticDiagPartials + 16;
+// Device address of that scratch on the current device (looked up once per
+// device with that device current).
+hipError_t static_diag_scratch(double **out);
 hipError_t launch_diag(const double *c, int N, int64_t n, double *partials, int nblk,
                        double *out, hipStream_t st);
 // Laplace jump on a dense FP64 p field of nx * ny * nz nodes (nz = 1 in

@@ -31,7 +31,7 @@ ERRORS_KEEP_TICKET = -6
 EXPORTS = [
     "nplbm_last_error", "nplbm_validate", "nplbm_footprint", "nplbm_create",
     "nplbm_set_fields", "nplbm_step", "nplbm_get_c", "nplbm_get_u", "nplbm_get_p",
-    "nplbm_diagnostics", "nplbm_laplace", "nplbm_laplace3", "nplbm_time", "nplbm_sync", "nplbm_destroy",
+    "nplbm_diagnostics", "nplbm_diagnostics_noalloc", "nplbm_laplace", "nplbm_laplace3", "nplbm_time", "nplbm_sync", "nplbm_destroy",
     "nplbm_state_bytes", "nplbm_get_state", "nplbm_set_state", "nplbm_device_copy",
     "nplbm_server_create", "nplbm_submit", "nplbm_server_pump", "nplbm_poll",
     "nplbm_result", "nplbm_server_stats", "nplbm_server_destroy",
@@ -88,6 +88,7 @@ def lib():
             "nplbm_get_u": ([vp, dp], c_int),
             "nplbm_get_p": ([vp, dp], c_int),
             "nplbm_diagnostics": ([vp, dp, dp, ctypes.POINTER(c_i64)], c_int),
+            "nplbm_diagnostics_noalloc": ([vp, vp], c_int),
             "nplbm_laplace3": ([vp] + [ctypes.c_double] * 5 + [dp], c_int),
             "nplbm_laplace": ([vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                ctypes.c_double, dp], c_int),
@@ -275,6 +276,15 @@ class Domain:
         bad = ctypes.c_int64()
         _check(lib().nplbm_diagnostics(self._h, _dp(mass), ctypes.byref(dev), ctypes.byref(bad)))
         return mass, dev.value, bad.value
+
+    def diagnostics_noalloc(self, out):
+        """nplbm_diagnostics_noalloc into ``out``, a float64 device tensor of
+        at least N + 2 elements (asynchronous on the domain's stream)."""
+        torch = _torch()
+        if out.dtype != torch.float64 or not out.is_cuda or out.numel() < self.N + 2 \
+                or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 device tensor of N + 2 elements")
+        _check(lib().nplbm_diagnostics_noalloc(self._h, ctypes.c_void_p(out.data_ptr())))
 
     def laplace(self, xc, yc, r_in, r_out, zc=None) -> float:
         """Laplace jump about (xc, yc) in 2-D, about (xc, yc, zc) in 3-D."""
