@@ -119,6 +119,16 @@ struct Scheme<2> {
 };
 // rings of the Remark 1 scheme: the products J~_b u_a and the previous u
 constexpr int kQR = 8, kUR = 4;
+// The two-hop schemes hold the pulls of a row for two iterations (lag 4).
+// The mixed scheme in FP64 at N = 5 cannot hold three register sets (it
+// runs one wave per SIMD with two sets and 480 registers), so there the set
+// pulled one iteration earlier waits in LDS, in per-thread slots: 10 (N - 1)
+// values (the 9 pulled populations and the stored phi of each phase).
+// Measured on the 2048^2 N = 5 workload: 59.2% of the HBM roofline against
+// 50.8% when the collision row is pulled a second time instead.  Remark 1
+// in FP64 at N = 5 measured slower that way (35%: its LDS then allows one
+// workgroup per CU), and FP32 holds three register sets.
+constexpr bool park_set(int N, int bytes, int gs) { return gs == 1 && N == 5 && bytes == 8; }
 // slot of march index m (m >= -16 R) in a ring of R rows
 template <int R>
 __device__ __forceinline__ int ring(int m) {
@@ -173,6 +183,8 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   __shared__ Real sC[kCR][M][kBW];
   __shared__ Real sQ[kR1 ? kQR : 1][4][kBW];  // J~_x u_x, J~_y u_x, J~_x u_y, J~_y u_y
   __shared__ Real sU[kR1 ? kUR : 1][2][kBW];  // previous u
+  constexpr bool kPark = park_set(N, (int)sizeof(Real), kGS);
+  __shared__ Real spark[kPark ? 10 * M : 1][kPark ? kBW * kRows : 1];  // parked pulls
 
   const int lane = threadIdx.x & (kBW - 1);
   // the row handled by this wave (uniform; said explicitly so every row,
@@ -377,8 +389,63 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
     sQ[sq][3][lane] = Jy * uy;
   };
 
+  // ---- stage G (mixed scheme): the phi gradients of march index mC ----
+  // eq:N40 below; phi is on the ring up to row mC + 4 once the first barrier
+  // of the iteration is passed, so these terms are summed before stage B:
+  // the two-hop stencils then do not share the registers of stage C with
+  // the NS arithmetic (with them in stage C, three register sets spilled
+  // 172 B per lane at N = 5 in FP32).  The sums are the ones stage C forms
+  // for the other schemes, over the phases in the same order.
+  struct PhiGrad {
+    Real grs, gys, Fxs, Fys;  // sum_i rA_i grad phi_i, sum_i C_i grad phi_i
+  };
+  auto grad2 = [&](const Real (*f)[M][kBW], int r0, int rN, int rS, int rN2, int rS2, int i,
+                   Real &gx, Real &gy) {
+    // eq:N40 summed over the D2Q9 directions.  Per direction c the
+    // difference is -z(x+2c) + 5 z(x+c) - 3 z(x) - z(x-c); with w_c, c_x
+    // and 1/(4 c_s^2) the z(x) terms cancel and opposite directions pair:
+    //   d/dx = [24 (E - W) - 4 (E2 - W2) + 6 (NE - NW + SE - SW)
+    //           - (NE2 - NW2 + SE2 - SW2)] / 48
+    // (E2 = z(x+2, y), NE2 = z(x+2, y+2), ...), and likewise d/dy.
+    const Real e = f[r0][i][lane + 1], w = f[r0][i][lane - 1];
+    const Real e2 = f[r0][i][lane + 2], w2 = f[r0][i][lane - 2];
+    const Real n = f[rN][i][lane], s = f[rS][i][lane];
+    const Real n2 = f[rN2][i][lane], s2 = f[rS2][i][lane];
+    const Real ne = f[rN][i][lane + 1], nw = f[rN][i][lane - 1];
+    const Real se = f[rS][i][lane + 1], sw = f[rS][i][lane - 1];
+    const Real ne2 = f[rN2][i][lane + 2], nw2 = f[rN2][i][lane - 2];
+    const Real se2 = f[rS2][i][lane + 2], sw2 = f[rS2][i][lane - 2];
+    gx = (Real(24) * (e - w) - Real(4) * (e2 - w2) + Real(6) * ((ne - nw) + (se - sw)) -
+          ((ne2 - nw2) + (se2 - sw2))) *
+         (Real(1) / Real(48));
+    gy = (Real(24) * (n - s) - Real(4) * (n2 - s2) + Real(6) * ((ne + nw) - (se + sw)) -
+          ((ne2 + nw2) - (se2 + sw2))) *
+         (Real(1) / Real(48));
+  };
+  auto stageG = [&](int mC) {
+    PhiGrad G{Real(0), Real(0), Real(0), Real(0)};
+    if constexpr (kTwoHop) {
+      if (!interior || mC < 0 || mC >= H) return G;
+      const int p0 = ring<kPR>(mC), pN = ring<kPR>(mC + dir), pS = ring<kPR>(mC - dir);
+      const int pN2 = ring<kPR>(mC + 2 * dir), pS2 = ring<kPR>(mC - 2 * dir);
+      const int q0 = ring<kCR>(mC);
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        Real gx, gy;
+        grad2(sphi, p0, pN, pS, pN2, pS2, i, gx, gy);
+        const Real Ci = sC[q0][i][lane];
+        G.grs += K.rA[i] * gx;
+        G.gys += K.rA[i] * gy;
+        G.Fxs += Ci * gx;
+        G.Fys += Ci * gy;
+      }
+    }
+    return G;
+  };
+
   // ---- stage C: collide march index mC with what was pulled for it ----
-  auto stageC = [&](int mC, const Pulled<M, Real> &P, const PulledNS<Real> &Q) {
+  auto stageC = [&](int mC, const Pulled<M, Real> &P, const PulledNS<Real> &Q,
+                    const PhiGrad &G) {
     if (!interior || mC < 0 || mC >= H) return;
     const int yp = row_of(mC);
     const int p0 = ring<kPR>(mC), pN = ring<kPR>(mC + dir), pS = ring<kPR>(mC - dir);
@@ -403,37 +470,13 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
         if constexpr (!kR1) grad(sC, q0, qN, qS, i, gCx[i], gCy[i]);
       }
     } else {
-      // eq:N40 summed over the D2Q9 directions.  Per direction c the
-      // difference is -z(x+2c) + 5 z(x+c) - 3 z(x) - z(x-c); with w_c, c_x
-      // and 1/(4 c_s^2) the z(x) terms cancel and opposite directions pair:
-      //   d/dx = [24 (E - W) - 4 (E2 - W2) + 6 (NE - NW + SE - SW)
-      //           - (NE2 - NW2 + SE2 - SW2)] / 48
-      // (E2 = z(x+2, y), NE2 = z(x+2, y+2), ...), and likewise d/dy.
-      const int pN2 = ring<kPR>(mC + 2 * dir), pS2 = ring<kPR>(mC - 2 * dir);
+      // the C gradients (eq:N40) here; the phi gradients came from stage G
       const int qN2 = ring<kCR>(mC + 2 * dir), qS2 = ring<kCR>(mC - 2 * dir);
-      auto grad = [&](const Real (*f)[M][kBW], int r0, int rN, int rS, int rN2, int rS2, int i,
-                      Real &gx, Real &gy) {
-        const Real e = f[r0][i][lane + 1], w = f[r0][i][lane - 1];
-        const Real e2 = f[r0][i][lane + 2], w2 = f[r0][i][lane - 2];
-        const Real n = f[rN][i][lane], s = f[rS][i][lane];
-        const Real n2 = f[rN2][i][lane], s2 = f[rS2][i][lane];
-        const Real ne = f[rN][i][lane + 1], nw = f[rN][i][lane - 1];
-        const Real se = f[rS][i][lane + 1], sw = f[rS][i][lane - 1];
-        const Real ne2 = f[rN2][i][lane + 2], nw2 = f[rN2][i][lane - 2];
-        const Real se2 = f[rS2][i][lane + 2], sw2 = f[rS2][i][lane - 2];
-        gx = (Real(24) * (e - w) - Real(4) * (e2 - w2) + Real(6) * ((ne - nw) + (se - sw)) -
-              ((ne2 - nw2) + (se2 - sw2))) *
-             (Real(1) / Real(48));
-        gy = (Real(24) * (n - s) - Real(4) * (n2 - s2) + Real(6) * ((ne + nw) - (se + sw)) -
-              ((ne2 + nw2) - (se2 + sw2))) *
-             (Real(1) / Real(48));
-      };
 #pragma unroll
       for (int i = 0; i < M; ++i) {
         phi[i] = sphi[p0][i][lane];
         Cv[i] = sC[q0][i][lane];
-        grad(sphi, p0, pN, pS, pN2, pS2, i, gpx[i], gpy[i]);
-        grad(sC, q0, qN, qS, qN2, qS2, i, gCx[i], gCy[i]);
+        grad2(sC, q0, qN, qS, qN2, qS2, i, gCx[i], gCy[i]);
       }
     }
     // density, relaxation, forces
@@ -444,14 +487,22 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
 #pragma unroll
     for (int i = 0; i < M; ++i) {
       rho += KD.rA[i] * phi[i];
-      grs += K.rA[i] * gpx[i];
-      gys += K.rA[i] * gpy[i];
-      Fxs += Cv[i] * gpx[i];
-      Fys += Cv[i] * gpy[i];
+      if constexpr (!kTwoHop) {
+        grs += K.rA[i] * gpx[i];
+        gys += K.rA[i] * gpy[i];
+        Fxs += Cv[i] * gpx[i];
+        Fys += Cv[i] * gpy[i];
+      }
       if constexpr (!kR1) {
         Jxs += K.Jc[i] * gCx[i];
         Jys += K.Jc[i] * gCy[i];
       }
+    }
+    if constexpr (kTwoHop) {
+      grs = G.grs;
+      gys = G.gys;
+      Fxs = G.Fxs;
+      Fys = G.Fys;
     }
     const Acc grx = grs, gry = gys, Jx = Jxs, Jy = Jys;
     Acc Fx = Fxs, Fy = Fys;
@@ -600,21 +651,51 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   //  - mixed and Remark 1, N <= 4: three sets (cur, mA - 2, mA - 4); the
   //    Remark 1 scheme runs stage J on rows mA - 2 behind a third barrier
   //    before the collision;
-  //  - mixed and Remark 1, N >= 5 (except Remark 1 in FP32 at N = 5): three
-  //    sets would spill or leave one wave per SIMD, so the collision row's
-  //    CH populations are pulled a second time (from L2 / MALL, 2 iterations
-  //    after the first pull) and one set suffices.  Measured on the 2048^2
-  //    N = 5 workload, mixed scheme: 45% of the HBM roofline in FP32 against
-  //    37% with three sets (the re-read costs the central scheme 13 points,
-  //    so it is used only here).  Remark 1 in FP32 still fits three sets at
-  //    N = 5 (229 VGPRs, two waves per SIMD): 56.8% against 45.3% with the
-  //    second pull.
+  //  - mixed and Remark 1 at N = 5 (except Remark 1 in FP32, which fits
+  //    three sets in 229 VGPRs): three register sets would spill (the mixed
+  //    scheme's two-hop stencils in stage C) or leave one wave per SIMD, so
+  //    two register sets, cur and old, are used; after the collision of
+  //    old, old takes the set parked in LDS one iteration earlier and cur is
+  //    parked in its place (each thread its own slots, so no barrier is
+  //    involved);
+  //  - mixed and Remark 1, N >= 6: the parked set would not fit in LDS, so
+  //    the collision row's CH populations are pulled a second time (from
+  //    L2 / MALL, 2 iterations after the first pull) and one set suffices
+  //    (the re-read costs the central scheme 13 points of the HBM roofline).
   constexpr int kRamp = S::kRamp, kLag = S::kLag;
-  constexpr bool kRepull = kGS != 0 && N >= 5 && !(kGS == 2 && sizeof(Real) == 4 && N == 5);
+  constexpr bool kRepull = kGS != 0 && N >= 6;
   const int J = (H + kRamp + kLag + 1) / 2;
   PulledNS<Real> ns;
   constexpr bool kPipeline = kGS == 0 && sizeof(Real) == 4 && N <= 5;
-  if constexpr (kRepull) {
+  if constexpr (kPark) {
+    Pulled<M, Real> cur, old;
+    const int slot = threadIdx.x;
+    for (int j = 0; j < J; ++j) {  // j is uniform over the block
+      const int mA = 2 * j - kRamp + ry;
+      pull_ch(mA, cur);
+      stageA(mA, cur);
+      __syncthreads();
+      pull_ns(mA - kLag, ns);
+      const PhiGrad g1 = stageG(mA - kLag);
+      stageB(mA - 1);
+      __syncthreads();
+      if constexpr (kR1) {
+        stageJ(mA - 2);
+        __syncthreads();
+      }
+      stageC(mA - kLag, old, ns, g1);
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+          old.h[i][k] = spark[i * 9 + k][slot];
+          spark[i * 9 + k][slot] = cur.h[i][k];
+        }
+        old.hi[i] = spark[9 * M + i][slot];
+        spark[9 * M + i][slot] = cur.hi[i];
+      }
+    }
+  } else if constexpr (kRepull) {
     // one register set: the CH populations of the collision row are loaded
     // again (from L2 / MALL) right after the first barrier
     Pulled<M, Real> buf;
@@ -624,6 +705,7 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
       stageA(mA, buf);
       __syncthreads();
       pull_ns(mA - kLag, ns);
+      const PhiGrad g1 = stageG(mA - kLag);
       pull_ch(mA - kLag, buf);
       stageB(mA - 1);
       __syncthreads();
@@ -631,7 +713,7 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
         stageJ(mA - 2);
         __syncthreads();
       }
-      stageC(mA - kLag, buf, ns);
+      stageC(mA - kLag, buf, ns, g1);
     }
   } else if constexpr (kGS != 0) {
     Pulled<M, Real> bufA, bufB, bufC;
@@ -641,13 +723,14 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
       stageA(mA, cur);
       __syncthreads();
       pull_ns(mA - kLag, ns);
+      const PhiGrad g1 = stageG(mA - kLag);
       stageB(mA - 1);
       __syncthreads();
       if constexpr (kR1) {
         stageJ(mA - 2);
         __syncthreads();
       }
-      stageC(mA - kLag, held, ns);
+      stageC(mA - kLag, held, ns, g1);
     };
     for (int j = 0; j < J; j += 3) {  // j is uniform over the block
       iteration(j, bufA, bufB);       // bufB holds the pulls of iteration j - 2
@@ -662,10 +745,11 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
       stageA(mA, cur);
       __syncthreads();
       pull_ns(mA - kLag, ns);
+      const PhiGrad g1 = stageG(mA - kLag);
       pull_ch(mA + 2, next);
       stageB(mA - 1);
       __syncthreads();
-      stageC(mA - kLag, held, ns);
+      stageC(mA - kLag, held, ns, g1);
     };
     pull_ch(ry - kRamp, bufA);
     for (int j = 0; j < J; j += 3) {  // j is uniform over the block
@@ -681,9 +765,10 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
       stageA(mA, cur);
       __syncthreads();
       pull_ns(mA - kLag, ns);
+      const PhiGrad g1 = stageG(mA - kLag);
       stageB(mA - 1);
       __syncthreads();
-      stageC(mA - kLag, held, ns);
+      stageC(mA - kLag, held, ns, g1);
     };
     for (int j = 0; j < J; j += 2) {  // j is uniform over the block
       iteration(j, bufA, bufB);
@@ -706,17 +791,22 @@ constexpr int lds_bytes(int N, int bytes, int bw, int gs) {
   return ((gs == 1 ? Scheme<1>::kPR + Scheme<1>::kCR
                    : (gs == 2 ? Scheme<2>::kPR + Scheme<2>::kCR : Scheme<0>::kPR + Scheme<0>::kCR)) *
               (N - 1) +
-          (gs == 2 ? 4 * kQR + 2 * kUR : 0)) *
+          (gs == 2 ? 4 * kQR + 2 * kUR : 0) +
+          (park_set(N, bytes, gs) ? 10 * (N - 1) * kRows : 0)) *
          bw * bytes;
 }
 // LDS budget of a workgroup: 64 KiB for the central scheme; 80 KiB for the
-// others (gfx950 has 160 KiB per CU, so two such workgroups still fit)
-constexpr int lds_budget(int gs) { return gs ? 80 * 1024 : 64 * 1024; }
+// others (gfx950 has 160 KiB per CU, so two such workgroups still fit);
+// 160 KiB with a parked set in FP32, where the registers allow one 512-thread
+// workgroup per CU anyway
+constexpr int lds_budget(int gs, int N, int bytes) {
+  return park_set(N, bytes, gs) && bytes == 4 ? 160 * 1024 : (gs ? 80 * 1024 : 64 * 1024);
+}
 // the widest row a (N, precision, scheme) is built for
 constexpr int max_bw(int N, int bytes, int gs) {
-  return lds_bytes(N, bytes, 256, gs) <= lds_budget(gs)
+  return lds_bytes(N, bytes, 256, gs) <= lds_budget(gs, N, bytes)
              ? 256
-             : (lds_bytes(N, bytes, 128, gs) <= lds_budget(gs) ? 128 : 64);
+             : (lds_bytes(N, bytes, 128, gs) <= lds_budget(gs, N, bytes) ? 128 : 64);
 }
 
 #if NPL_GS == 0

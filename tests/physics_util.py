@@ -152,3 +152,36 @@ def centroid_velocity(c, u, k):
     """Velocity of the centroid of phase k: sum c_k u / sum c_k."""
     m = c[k].sum()
     return (c[k] * u[0]).sum() / m, (c[k] * u[1]).sum() / m
+
+
+def order_parameters(c, rho):
+    """phi_i of eq:N12 from the volume fractions (the inverse the initial
+    state uses): phi_i = (rho_i c_i - rho_N c_N - b_i) / a_i."""
+    rho = np.asarray(rho, dtype=float)
+    a = 0.5 * (rho[:-1] + rho[-1])
+    b = 0.5 * (rho[:-1] - rho[-1])
+    return np.stack([(rho[i] * c[i] - rho[-1] * c[-1] - b[i]) / a[i]
+                     for i in range(len(rho) - 1)])
+
+
+def line_tension(c_line, rho, lam):
+    """Tension of an interface crossed by the 1-D profile c_line (N, n),
+    taken along its normal: at equilibrium the gradient and bulk parts of
+    the free energy are equal (equipartition), so sigma = int sum_ij
+    lambda_ij phi_i' phi_j' (central differences, unit spacing)."""
+    d = np.gradient(order_parameters(c_line, rho), axis=1)
+    return float(np.einsum("ij,in,jn->n", lam, d, d).sum())
+
+
+def lens_interface_lines(c):
+    """Profiles across the three interfaces of an equilibrated lens (phase 1
+    lens at the flat interface between phase 2 above and phase 3 below):
+    the column far from the lens (x = 0) crosses 2|3, the column through the
+    lens centre crosses 1|2 above the flat level and 1|3 below it.  Returns
+    {(k, l): (profile, index of the third phase)} with 0-based phases."""
+    ny, nx = c.shape[1:]
+    yf = int(round(flat_level(c)))
+    xc = nx // 2
+    return {(1, 2): (c[:, :, 0], 0),
+            (0, 1): (c[:, yf + 1:, xc], 2),
+            (0, 2): (c[:, :yf, xc], 1)}

@@ -5,7 +5,9 @@ droplet and bubble, eq:N38), the puddle thickness against de Gennes' balance
 the falling droplet that Sec. 4.3 reports.
 
 Measured on MI355X: puddle R = 40 on 600 x 200, g = 2e-5: H = 28.88 against
-28.87; g = 5e-5: 18.73 against 18.26.  Four-phase run to t = 12.25 (time
+28.87; g = 5e-5: 18.73 against 18.26; at g = 2e-5 with sigma_13 = 0.006, 0.008,
+0.012, 0.014 (sigma_12 = sigma_23 = 0.01): 22.78, 26.0, 31.6, 34.1 against
+22.36, 25.82, 31.62, 34.16 after 300 000 steps.  Four-phase run to t = 12.25 (time
 unit sqrt(D / g)): mean droplet speed over t = 6.5 .. 12.25 is 0.365 sqrt(gD)
 for sigma_13 = 0.01 and 0.313 for sigma_13 = 0.006."""
 import numpy as np
@@ -77,3 +79,24 @@ def test_four_phase_droplet_falls_slower_with_lower_tension():
         speed[s13] = np.mean(late)
         print(f"sigma_13={s13}: mean late fall speed {speed[s13]:.3f}", flush=True)
     assert speed[0.006] < 0.95 * speed[0.01]
+
+
+def test_puddle_thickness_against_sigma13():
+    """H(sigma_13) at g = 2e-5 (R = 40 on 600 x 200, rho = 3 : 1 : 6,
+    sigma_12 = sigma_23 = 0.01): de Gennes' balance (eq:N37 with the upper
+    phase's density kept) gives H^2 proportional to the spreading term
+    sigma_12 + sigma_13 - sigma_23 = sigma_13."""
+    H = {}
+    for s13, tol in ((0.006, 0.03), (0.014, 0.02)):
+        w = W.floating_puddle(600, 200, R=40.0, g=2e-5, sigma=(0.01, s13, 0.01))
+        print(f"case puddle sigma_13={s13} 600x200 steps=300000", flush=True)
+        d = gpu_domain(w)
+        d.step(300_000)
+        _, _, bad = d.diagnostics()
+        H[s13] = puddle_thickness(d.get_c())
+        d.close()
+        assert bad == 0
+        Hth = de_gennes_thickness(0.01, s13, 0.01, 3.0, 1.0, 6.0, 2e-5)
+        print(f"  H={H[s13]:.3f} de Gennes {Hth:.3f}", flush=True)
+        assert abs(H[s13] - Hth) / Hth < tol
+    assert H[0.014] / H[0.006] == pytest.approx(np.sqrt(0.014 / 0.006), rel=0.03)

@@ -79,3 +79,24 @@ def test_puddle_thickness_measure():
     c1 = np.clip(np.minimum(y - 20.3, 35.8 - y) / 3.0 + 0.5, 0.0, 1.0)
     c = np.stack([c1, 1 - c1, np.zeros_like(c1)])
     assert puddle_thickness(c) == pytest.approx(15.5, abs=1e-9)
+
+
+def test_line_tension_of_the_equilibrium_profile():
+    """The equipartition measure on the continuum equilibrium profile of a
+    flat two-phase interface, phi = tanh(x / (sqrt 2 eta)) with lambda =
+    (9/2)(eta^2 / beta^2) sigma^2 and beta^2 = 3 sqrt 2 sigma eta (eq:N14,
+    eq:N36): int lambda phi'^2 dx = lambda 2 sqrt 2 / (3 eta) = sigma.
+    Equal densities (phi = 2 c - 1).  The central differences leave a
+    relative error that falls as 1 / W^2 (-0.41% at W = 16)."""
+    from physics_util import line_tension
+    sigma = 1e-3
+    err = {}
+    for Wd in (16.0, 32.0):
+        eta = Wd / (2 * np.sqrt(2))
+        beta2 = 3 * np.sqrt(2) * sigma * eta
+        lam = np.array([[4.5 * eta ** 2 / beta2 * sigma ** 2]])
+        x = np.arange(-400, 401, dtype=float)
+        c1 = 0.5 + 0.5 * np.tanh(2 * x / Wd)
+        err[Wd] = line_tension(np.stack([c1, 1 - c1]), (1.0, 1.0), lam) / sigma - 1
+    assert abs(err[16.0]) < 6e-3
+    assert err[32.0] / err[16.0] == pytest.approx(0.25, rel=0.05)
