@@ -119,16 +119,6 @@ struct Scheme<2> {
 };
 // rings of the Remark 1 scheme: the products J~_b u_a and the previous u
 constexpr int kQR = 8, kUR = 4;
-// The two-hop schemes hold the pulls of a row for two iterations (lag 4).
-// The mixed scheme in FP64 at N = 5 cannot hold three register sets (it
-// runs one wave per SIMD with two sets and 480 registers), so there the set
-// pulled one iteration earlier waits in LDS, in per-thread slots: 10 (N - 1)
-// values (the 9 pulled populations and the stored phi of each phase).
-// Measured on the 2048^2 N = 5 workload: 59.2% of the HBM roofline against
-// 50.8% when the collision row is pulled a second time instead.  Remark 1
-// in FP64 at N = 5 measured slower that way (35%: its LDS then allows one
-// workgroup per CU), and FP32 holds three register sets.
-constexpr bool park_set(int N, int bytes, int gs) { return gs == 1 && N == 5 && bytes == 8; }
 // slot of march index m (m >= -16 R) in a ring of R rows
 template <int R>
 __device__ __forceinline__ int ring(int m) {
@@ -183,8 +173,6 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   __shared__ Real sC[kCR][M][kBW];
   __shared__ Real sQ[kR1 ? kQR : 1][4][kBW];  // J~_x u_x, J~_y u_x, J~_x u_y, J~_y u_y
   __shared__ Real sU[kR1 ? kUR : 1][2][kBW];  // previous u
-  constexpr bool kPark = park_set(N, (int)sizeof(Real), kGS);
-  __shared__ Real spark[kPark ? 10 * M : 1][kPark ? kBW * kRows : 1];  // parked pulls
 
   const int lane = threadIdx.x & (kBW - 1);
   // the row handled by this wave (uniform; said explicitly so every row,
@@ -648,54 +636,27 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   //    mA, next = mA + 2, held = mA - 2);
   //  - central otherwise: two sets (cur, held = mA - 2); three would halve
   //    the occupancy or spill;
-  //  - mixed and Remark 1, N <= 4: three sets (cur, mA - 2, mA - 4); the
+  //  - mixed and Remark 1, N <= 5: three sets (cur, mA - 2, mA - 4); the
   //    Remark 1 scheme runs stage J on rows mA - 2 behind a third barrier
-  //    before the collision;
-  //  - mixed and Remark 1 at N = 5 (except Remark 1 in FP32, which fits
-  //    three sets in 229 VGPRs): three register sets would spill (the mixed
-  //    scheme's two-hop stencils in stage C) or leave one wave per SIMD, so
-  //    two register sets, cur and old, are used; after the collision of
-  //    old, old takes the set parked in LDS one iteration earlier and cur is
-  //    parked in its place (each thread its own slots, so no barrier is
-  //    involved);
-  //  - mixed and Remark 1, N >= 6: the parked set would not fit in LDS, so
-  //    the collision row's CH populations are pulled a second time (from
-  //    L2 / MALL, 2 iterations after the first pull) and one set suffices
-  //    (the re-read costs the central scheme 13 points of the HBM roofline).
+  //    before the collision.  At N = 5 the three sets fit: in FP32 in two waves per SIMD once
+  //    the mixed scheme's phi gradients are summed in stage G (245 VGPRs;
+  //    Remark 1 229), in FP64 in one wave per SIMD with AGPRs (mixed 436
+  //    registers, Remark 1 412, no spill).  Measured on the 2048^2 N = 5
+  //    workload against pulling the collision row a second time: mixed FP32
+  //    55.0% against 45.9% of the HBM roofline, mixed FP64 63.6% against
+  //    50.8%, Remark 1 FP64 63.9% against 49.8%.  Keeping the set pulled one
+  //    iteration earlier in LDS instead of registers measured 59.7% (mixed
+  //    FP64);
+  //  - mixed and Remark 1, N >= 6: the collision row's CH populations are
+  //    pulled a second time (from L2 / MALL, 2 iterations after the first
+  //    pull) and one set suffices (the re-read costs the central scheme 13
+  //    points of the HBM roofline).
   constexpr int kRamp = S::kRamp, kLag = S::kLag;
   constexpr bool kRepull = kGS != 0 && N >= 6;
   const int J = (H + kRamp + kLag + 1) / 2;
   PulledNS<Real> ns;
   constexpr bool kPipeline = kGS == 0 && sizeof(Real) == 4 && N <= 5;
-  if constexpr (kPark) {
-    Pulled<M, Real> cur, old;
-    const int slot = threadIdx.x;
-    for (int j = 0; j < J; ++j) {  // j is uniform over the block
-      const int mA = 2 * j - kRamp + ry;
-      pull_ch(mA, cur);
-      stageA(mA, cur);
-      __syncthreads();
-      pull_ns(mA - kLag, ns);
-      const PhiGrad g1 = stageG(mA - kLag);
-      stageB(mA - 1);
-      __syncthreads();
-      if constexpr (kR1) {
-        stageJ(mA - 2);
-        __syncthreads();
-      }
-      stageC(mA - kLag, old, ns, g1);
-#pragma unroll
-      for (int i = 0; i < M; ++i) {
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-          old.h[i][k] = spark[i * 9 + k][slot];
-          spark[i * 9 + k][slot] = cur.h[i][k];
-        }
-        old.hi[i] = spark[9 * M + i][slot];
-        spark[9 * M + i][slot] = cur.hi[i];
-      }
-    }
-  } else if constexpr (kRepull) {
+  if constexpr (kRepull) {
     // one register set: the CH populations of the collision row are loaded
     // again (from L2 / MALL) right after the first barrier
     Pulled<M, Real> buf;
@@ -791,22 +752,17 @@ constexpr int lds_bytes(int N, int bytes, int bw, int gs) {
   return ((gs == 1 ? Scheme<1>::kPR + Scheme<1>::kCR
                    : (gs == 2 ? Scheme<2>::kPR + Scheme<2>::kCR : Scheme<0>::kPR + Scheme<0>::kCR)) *
               (N - 1) +
-          (gs == 2 ? 4 * kQR + 2 * kUR : 0) +
-          (park_set(N, bytes, gs) ? 10 * (N - 1) * kRows : 0)) *
+          (gs == 2 ? 4 * kQR + 2 * kUR : 0)) *
          bw * bytes;
 }
 // LDS budget of a workgroup: 64 KiB for the central scheme; 80 KiB for the
-// others (gfx950 has 160 KiB per CU, so two such workgroups still fit);
-// 160 KiB with a parked set in FP32, where the registers allow one 512-thread
-// workgroup per CU anyway
-constexpr int lds_budget(int gs, int N, int bytes) {
-  return park_set(N, bytes, gs) && bytes == 4 ? 160 * 1024 : (gs ? 80 * 1024 : 64 * 1024);
-}
+// others (gfx950 has 160 KiB per CU, so two such workgroups still fit)
+constexpr int lds_budget(int gs) { return gs ? 80 * 1024 : 64 * 1024; }
 // the widest row a (N, precision, scheme) is built for
 constexpr int max_bw(int N, int bytes, int gs) {
-  return lds_bytes(N, bytes, 256, gs) <= lds_budget(gs, N, bytes)
+  return lds_bytes(N, bytes, 256, gs) <= lds_budget(gs)
              ? 256
-             : (lds_bytes(N, bytes, 128, gs) <= lds_budget(gs, N, bytes) ? 128 : 64);
+             : (lds_bytes(N, bytes, 128, gs) <= lds_budget(gs) ? 128 : 64);
 }
 
 #if NPL_GS == 0
