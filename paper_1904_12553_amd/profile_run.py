@@ -36,6 +36,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--side", type=int, default=2048)
     ap.add_argument("--precision", type=int, default=32)
+    ap.add_argument("--scheme", choices=["central", "mixed", "remark1"], default="central",
+                    help="2-D step kernel: eq:N31a, eq:N40 gradients, or Remark 1's force")
     ap.add_argument("--mib", type=int, default=1024)
     args = ap.parse_args()
     import torch
@@ -70,7 +72,8 @@ def main():
              3: lambda: W.static_sphere(256, R=64.0)}[args.n3]()
     else:
         w = W.bands_and_droplets(args.side, accept=P.accepts)
-    d = P.Domain(precision=args.precision, **w.params())
+    over = {"central": {}, "mixed": {"grad_scheme": 1}, "remark1": {"force_form": 1}}[args.scheme]
+    d = P.Domain(precision=args.precision, **dict(w.params(), **over))
     d.set_fields(w.c, w.u)
     os.environ["NPLBM_NO_GRAPH"] = "1"
     d.step(args.steps)
