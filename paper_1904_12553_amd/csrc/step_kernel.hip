@@ -643,8 +643,9 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   //    Remark 1 229), in FP64 in one wave per SIMD with AGPRs (mixed 436
   //    registers, Remark 1 412, no spill).  Measured on the 2048^2 N = 5
   //    workload against pulling the collision row a second time: mixed FP32
-  //    55.0% against 45.9% of the HBM roofline, mixed FP64 63.6% against
-  //    50.8%, Remark 1 FP64 63.9% against 49.8%.  Keeping the set pulled one
+  //    55.0% against 45.9% of the HBM roofline with 256-thread rows (58.2%
+  //    with 128-thread rows), mixed FP64 63.6% against 50.8%, Remark 1 FP64
+  //    63.9% against 49.8%.  Keeping the set pulled one
   //    iteration earlier in LDS instead of registers measured 59.7% (mixed
   //    FP64);
   //  - mixed and Remark 1, N >= 6: the collision row's CH populations are
