@@ -466,10 +466,13 @@ StepGeom step_geom(int N, int precision, int scheme) {
     g.bw = (b == 128 || b == 256) ? b : 64;
   }
   g.bw = std::min(g.bw, step_max_bw(N, precision, scheme));
-  g.tx = ((g.bw - 2 * g.halo) / unit) * unit;
+  // rows of interior lanes hold no halo columns (their halo phi is pulled
+  // by lanes per direction); the other rows hold theirs
+  const int cols = interior_lanes(N, precision / 8, scheme) ? g.bw : g.bw - 2 * g.halo;
+  g.tx = (cols / unit) * unit;
   if (const char *e = std::getenv("NPLBM_TX")) g.tx = std::atoi(e);
   if (g.tx < 8) g.tx = 8;
-  if (g.tx > g.bw - 2 * g.halo) g.tx = g.bw - 2 * g.halo;
+  if (g.tx > cols) g.tx = cols;
   g.unit = unit;
   return g;
 }

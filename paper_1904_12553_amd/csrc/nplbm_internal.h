@@ -16,7 +16,7 @@ constexpr int kRows = 2;  // rows per marching iteration (one or more waves per 
 // gradients of eq:N40); lanes beyond that stay idle.
 struct StepGeom {
   int bw;    // threads per row (64, 128 or 256)
-  int tx;    // maximum interior columns per strip (<= bw - 2 halo)
+  int tx;    // maximum interior columns per strip (<= bw, or bw - 2 halo when the rows hold their halo)
   int unit;  // strip widths are multiples of this many columns (one cache line)
   int halo;  // halo columns on each side
 };
@@ -30,6 +30,15 @@ constexpr int kGradMixed = 1;
 constexpr int kSchemeCentral = 0;
 constexpr int kSchemeMixed = 1;
 constexpr int kSchemeRemark1 = 2;
+// Whether every lane of a step-kernel row owns an interior column (the
+// x-halo phi then comes from lanes that each pull one population of a halo
+// node): the central scheme in FP32 for N <= 5 and in FP64 for N <= 3.
+// Elsewhere the rows hold their halo columns; with more phases the extra
+// registers of the halo pull cost more than the wider strips gain (FP64
+// N = 7 spilled).
+constexpr bool interior_lanes(int N, int bytes, int scheme) {
+  return scheme == kSchemeCentral && N <= (bytes == 4 ? 5 : 3);
+}
 // Geometry used for N phases at a precision (32 / 64) and scheme;
 // NPLBM_BW and NPLBM_TX override.
 StepGeom step_geom(int N, int precision, int scheme);

@@ -169,23 +169,34 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   const uint32_t rbh = (uint32_t)D->rs[0] * SZ, rbg = (uint32_t)D->rs[1] * SZ,
                  rbp = (uint32_t)D->rs[2] * SZ;
 
-  __shared__ Real sphi[kPR][M][kBW];
-  __shared__ Real sC[kCR][M][kBW];
-  __shared__ Real sQ[kR1 ? kQR : 1][4][kBW];  // J~_x u_x, J~_y u_x, J~_x u_y, J~_y u_y
-  __shared__ Real sU[kR1 ? kUR : 1][2][kBW];  // previous u
+  // Lane layout.  Interior lanes (interior_lanes: the central scheme at
+  // N <= 5 in FP32, N <= 3 in FP64): lane l owns interior column x0 + l,
+  // ring column l + kHalo, so a strip has up to kBW interior columns and
+  // every row of loads and stores starts on the strip's first cache line;
+  // phi of the 2 kHalo halo columns is pulled one lane per (halo node,
+  // direction) (halo_pull, halo_phi).  Otherwise lane l owns column
+  // x0 - kHalo + l, and the halo lanes pull their nodes like the interior
+  // ones and do not collide.
+  constexpr bool kIL = interior_lanes(N, sizeof(Real), kGS);
+  constexpr int kRW = kIL ? kBW + 2 * kHalo : kBW;  // ring row width
+  __shared__ Real sphi[kPR][M][kRW];
+  __shared__ Real sC[kCR][M][kRW];
+  __shared__ Real sQ[kR1 ? kQR : 1][4][kRW];  // J~_x u_x, J~_y u_x, J~_x u_y, J~_y u_y
+  __shared__ Real sU[kR1 ? kUR : 1][2][kRW];  // previous u
 
   const int lane = threadIdx.x & (kBW - 1);
+  const int pos = kIL ? lane + kHalo : lane;  // ring column
   // the row handled by this wave (uniform; said explicitly so every row,
   // bounce-back and plane decision stays in scalar registers)
   const int ry = __builtin_amdgcn_readfirstlane(threadIdx.x / kBW);
-  const int xl = sd.x0 - kHalo + lane;
+  const int xl = kIL ? sd.x0 + lane : sd.x0 - kHalo + lane;
   int xc = xl % nx;
   if (xc < 0) xc += nx;
   const uint32_t xcu = (uint32_t)xc * SZ;                              // byte offsets
   const uint32_t xw = (xc == 0 ? (uint32_t)(nx - 1) : (uint32_t)xc - 1) * SZ;  // x - 1
   const uint32_t xe = (xc == nx - 1 ? 0u : (uint32_t)xc + 1) * SZ;             // x + 1
   const int ncol = sd.x1 - sd.x0;  // interior columns of this strip
-  const bool interior = lane >= kHalo && lane < ncol + kHalo;
+  const bool interior = kIL ? lane < ncol : (lane >= kHalo && lane < ncol + kHalo);
   const int H = sd.y1 - sd.y0;
   const int dir = sd.dir;
 
@@ -283,11 +294,84 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   // ---- stage A: phi of march index mA -> LDS ----
   auto stageA = [&](int mA, const Pulled<M, Real> &cur) {
     const int slot = ring<kPR>(mA);
+    // (lanes past a ragged strip end would overwrite the right halo)
+    if (!kIL || lane < ncol)
 #pragma unroll
-    for (int i = 0; i < M; ++i) sphi[slot][i][lane] = cur.hi[i] + lo_sum(cur.h[i]);  // eq:N28
+      for (int i = 0; i < M; ++i) sphi[slot][i][pos] = cur.hi[i] + lo_sum(cur.h[i]);  // eq:N28
     if constexpr (kR1) {
-      sU[ring<kUR>(mA)][0][lane] = cur.pu[0];
-      sU[ring<kUR>(mA)][1][lane] = cur.pu[1];
+      sU[ring<kUR>(mA)][0][pos] = cur.pu[0];
+      sU[ring<kUR>(mA)][1][pos] = cur.pu[1];
+    }
+  };
+
+  // ---- x-halo phi of the central scheme ----
+  // Phase i of the kNH halo nodes of a row (columns x0 - 2, x0 - 1, x1,
+  // x1 + 1) is pulled by one wave of the row: lane t < 9 kNH pulls
+  // direction t % 9 of halo node t / 9 and lane 9 kNH + n the stored phi of
+  // node n, so a phase costs one load instruction instead of the 9 of a
+  // lane per node.  The row's waves share the phases (the wave wv of the
+  // row takes i = wv, wv + kNW, ...).  halo_phi then sums each node's
+  // values in the order of stage A, so a halo phi equals, bit for bit, the
+  // phi the neighbouring strip computes for that node.
+  constexpr int kNH = 2 * kHalo;                      // halo nodes per row
+  constexpr int kNW = kBW / 64;                       // waves per row
+  constexpr int kHP = kIL ? (M + kNW - 1) / kNW : 1;  // phases per wave
+  __shared__ Real shalo[kIL ? kRows * kNW : 1][10 * kNH];
+  const int wv = __builtin_amdgcn_readfirstlane((threadIdx.x % kBW) / 64);  // wave in the row
+  auto halo_pull = [&](int m, Real (&hv)[kHP]) {
+    if constexpr (kIL) {
+      const int yp = phys_row(row_of(m));
+      const int wl = threadIdx.x & 63;  // lane in the wave
+      if (wl < 10 * kNH) {
+        const int hn = wl < 9 * kNH ? wl / 9 : wl - 9 * kNH;  // halo node of this lane
+        const int hk = wl < 9 * kNH ? wl % 9 : -1;           // its direction (-1: stored phi)
+        int hxc = (hn < kHalo ? sd.x0 - kHalo + hn : sd.x1 + hn - kHalo) % nx;
+        if (hxc < 0) hxc += nx;
+        // source node and direction (bounce-back beyond a wall), as src_of
+        int sy = yp, sx = hxc, kk = hk;
+        if (hk > 0) {
+          const int cx = cxk(hk), cy = cyk(hk);
+          const int ys = yp - cy;
+          if (wall && (ys < 0 || ys >= ny)) {
+            kk = oppk(hk);
+          } else {
+            sy = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
+            sx = hxc - cx;
+            sx = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
+          }
+        }
+        typedef const __attribute__((address_space(1))) char GC;
+        GC *base = hk >= 0 ? (GC *)hs + (size_t)sy * rbh + (size_t)sx * SZ
+                           : (GC *)pvs + (size_t)yp * rbp + (size_t)hxc * SZ;
+#pragma unroll
+        for (int q = 0; q < kHP; ++q) {
+          const int i = wv + q * kNW;
+          if (i < M) {
+            const uint32_t plane = hk >= 0 ? (uint32_t)(i * 9 + kk) : (uint32_t)i;
+            hv[q] = *(const __attribute__((address_space(1))) Real *)(base + (size_t)plane * pb);
+          }
+        }
+      }
+    }
+  };
+  auto halo_phi = [&](int mA, const Real (&hv)[kHP]) {
+    if constexpr (kIL) {
+      const int slot = ring<kPR>(mA);
+      const int wl = threadIdx.x & 63;
+      Real *sh = shalo[ry * kNW + wv];
+#pragma unroll
+      for (int q = 0; q < kHP; ++q) {
+        const int i = wv + q * kNW;
+        if (i < M) {
+          if (wl < 10 * kNH) sh[wl] = hv[q];
+          if (wl < kNH) {
+            Real lo = sh[9 * wl];
+#pragma unroll
+            for (int k = 1; k < 9; ++k) lo += sh[9 * wl + k];
+            sphi[slot][i][wl < kHalo ? wl : ncol + wl] = sh[9 * kNH + wl] + lo;  // eq:N28
+          }
+        }
+      }
     }
   };
 
@@ -304,7 +388,6 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   // neighbour the march has not pulled yet (a strip starting one row
   // inside the wall).
   auto stageB = [&](int mB) {
-    if (lane < 1 || lane > ncol + 2 * kHalo - 2) return;
     int me = mB;
     if (kGS == 0 && wall) {
       const int r = row_of(mB);
@@ -312,36 +395,46 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
       else if (r >= ny) me = mB - dir;   // ghost above row ny-1
     }
     const int s0 = ring<kPR>(me), s1 = ring<kPR>(me + 1), s2 = ring<kPR>(me - 1);
-    Real phi[M], lap[M];
-#pragma unroll
-    for (int i = 0; i < M; ++i) {
-      const Real c = sphi[s0][i][lane];
-      const Real e = sphi[s0][i][lane + 1], w = sphi[s0][i][lane - 1];
-      const Real n = sphi[s1][i][lane], s = sphi[s2][i][lane];
-      const Real ne = sphi[s1][i][lane + 1], nw = sphi[s1][i][lane - 1];
-      const Real se = sphi[s2][i][lane + 1], sw = sphi[s2][i][lane - 1];
-      // eq:N31b on D2Q9: (4 sum_axis + sum_diag - 20 zeta) / 6
-      lap[i] = (Real(4) * ((e + w) + (n + s)) + ((ne + nw) + (se + sw)) - Real(20) * c) *
-               (Real(1) / Real(6));
-      phi[i] = c;
-    }
-    Real wv[N];
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-      Real ck = K.ca[k];
-#pragma unroll
-      for (int i = 0; i < M; ++i) ck += K.cA[k][i] * phi[i];
-      wv[k] = ck * (Real(1) - ck) * (Real(1) - Real(2) * ck);
-    }
     const int sc = ring<kCR>(mB);
+    // C at ring column x
+    auto chem = [&](int x) {
+      Real phi[M], lap[M];
 #pragma unroll
-    for (int i = 0; i < M; ++i) {
-      Real Ci = Real(0);
+      for (int i = 0; i < M; ++i) {
+        const Real c = sphi[s0][i][x];
+        const Real e = sphi[s0][i][x + 1], w = sphi[s0][i][x - 1];
+        const Real n = sphi[s1][i][x], s = sphi[s2][i][x];
+        const Real ne = sphi[s1][i][x + 1], nw = sphi[s1][i][x - 1];
+        const Real se = sphi[s2][i][x + 1], sw = sphi[s2][i][x - 1];
+        // eq:N31b on D2Q9: (4 sum_axis + sum_diag - 20 zeta) / 6
+        lap[i] = (Real(4) * ((e + w) + (n + s)) + ((ne + nw) + (se + sw)) - Real(20) * c) *
+                 (Real(1) / Real(6));
+        phi[i] = c;
+      }
+      Real wv[N];
 #pragma unroll
-      for (int j = 0; j < M; ++j) Ci -= K.lam[i][j] * lap[j];
+      for (int k = 0; k < N; ++k) {
+        Real ck = K.ca[k];
 #pragma unroll
-      for (int k = 0; k < N; ++k) Ci += K.KH[k][i] * wv[k];
-      sC[sc][i][lane] = Ci;
+        for (int i = 0; i < M; ++i) ck += K.cA[k][i] * phi[i];
+        wv[k] = ck * (Real(1) - ck) * (Real(1) - Real(2) * ck);
+      }
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        Real Ci = Real(0);
+#pragma unroll
+        for (int j = 0; j < M; ++j) Ci -= K.lam[i][j] * lap[j];
+#pragma unroll
+        for (int k = 0; k < N; ++k) Ci += K.KH[k][i] * wv[k];
+        sC[sc][i][x] = Ci;
+      }
+    };
+    if constexpr (kIL) {
+      // ring columns 1 .. ncol + 2: lane l takes l + 1, and lanes 0 and 1
+      // also the last two of a full-width strip
+      for (int x = lane + 1; x <= ncol + 2; x += kBW) chem(x);
+    } else {
+      if (lane >= 1 && lane <= ncol + 2 * kHalo - 2) chem(pos);
     }
   };
 
@@ -360,21 +453,21 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
     Real Jx = Real(0), Jy = Real(0);
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-      const Real e = sC[q0][i][lane + 1], w = sC[q0][i][lane - 1];
-      const Real n = sC[qN][i][lane], s = sC[qS][i][lane];
-      const Real ne = sC[qN][i][lane + 1], nw = sC[qN][i][lane - 1];
-      const Real se = sC[qS][i][lane + 1], sw = sC[qS][i][lane - 1];
+      const Real e = sC[q0][i][pos + 1], w = sC[q0][i][pos - 1];
+      const Real n = sC[qN][i][pos], s = sC[qS][i][pos];
+      const Real ne = sC[qN][i][pos + 1], nw = sC[qN][i][pos - 1];
+      const Real se = sC[qS][i][pos + 1], sw = sC[qS][i][pos - 1];
       const Real gx = (Real(4) * (e - w) + ((ne - nw) + (se - sw))) * (Real(1) / Real(12));
       const Real gy = (Real(4) * (n - s) + ((ne + nw) - (se + sw))) * (Real(1) / Real(12));
       Jx += K.Jc[i] * gx;
       Jy += K.Jc[i] * gy;
     }
     const int su = ring<kUR>(mJ), sq = ring<kQR>(mJ);
-    const Real ux = sU[su][0][lane], uy = sU[su][1][lane];
-    sQ[sq][0][lane] = Jx * ux;
-    sQ[sq][1][lane] = Jy * ux;
-    sQ[sq][2][lane] = Jx * uy;
-    sQ[sq][3][lane] = Jy * uy;
+    const Real ux = sU[su][0][pos], uy = sU[su][1][pos];
+    sQ[sq][0][pos] = Jx * ux;
+    sQ[sq][1][pos] = Jy * ux;
+    sQ[sq][2][pos] = Jx * uy;
+    sQ[sq][3][pos] = Jy * uy;
   };
 
   // ---- stage G (mixed scheme): the phi gradients of march index mC ----
@@ -387,7 +480,7 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   struct PhiGrad {
     Real grs, gys, Fxs, Fys;  // sum_i rA_i grad phi_i, sum_i C_i grad phi_i
   };
-  auto grad2 = [&](const Real (*f)[M][kBW], int r0, int rN, int rS, int rN2, int rS2, int i,
+  auto grad2 = [&](const Real (*f)[M][kRW], int r0, int rN, int rS, int rN2, int rS2, int i,
                    Real &gx, Real &gy) {
     // eq:N40 summed over the D2Q9 directions.  Per direction c the
     // difference is -z(x+2c) + 5 z(x+c) - 3 z(x) - z(x-c); with w_c, c_x
@@ -395,14 +488,14 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
     //   d/dx = [24 (E - W) - 4 (E2 - W2) + 6 (NE - NW + SE - SW)
     //           - (NE2 - NW2 + SE2 - SW2)] / 48
     // (E2 = z(x+2, y), NE2 = z(x+2, y+2), ...), and likewise d/dy.
-    const Real e = f[r0][i][lane + 1], w = f[r0][i][lane - 1];
-    const Real e2 = f[r0][i][lane + 2], w2 = f[r0][i][lane - 2];
-    const Real n = f[rN][i][lane], s = f[rS][i][lane];
-    const Real n2 = f[rN2][i][lane], s2 = f[rS2][i][lane];
-    const Real ne = f[rN][i][lane + 1], nw = f[rN][i][lane - 1];
-    const Real se = f[rS][i][lane + 1], sw = f[rS][i][lane - 1];
-    const Real ne2 = f[rN2][i][lane + 2], nw2 = f[rN2][i][lane - 2];
-    const Real se2 = f[rS2][i][lane + 2], sw2 = f[rS2][i][lane - 2];
+    const Real e = f[r0][i][pos + 1], w = f[r0][i][pos - 1];
+    const Real e2 = f[r0][i][pos + 2], w2 = f[r0][i][pos - 2];
+    const Real n = f[rN][i][pos], s = f[rS][i][pos];
+    const Real n2 = f[rN2][i][pos], s2 = f[rS2][i][pos];
+    const Real ne = f[rN][i][pos + 1], nw = f[rN][i][pos - 1];
+    const Real se = f[rS][i][pos + 1], sw = f[rS][i][pos - 1];
+    const Real ne2 = f[rN2][i][pos + 2], nw2 = f[rN2][i][pos - 2];
+    const Real se2 = f[rS2][i][pos + 2], sw2 = f[rS2][i][pos - 2];
     gx = (Real(24) * (e - w) - Real(4) * (e2 - w2) + Real(6) * ((ne - nw) + (se - sw)) -
           ((ne2 - nw2) + (se2 - sw2))) *
          (Real(1) / Real(48));
@@ -421,7 +514,7 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
       for (int i = 0; i < M; ++i) {
         Real gx, gy;
         grad2(sphi, p0, pN, pS, pN2, pS2, i, gx, gy);
-        const Real Ci = sC[q0][i][lane];
+        const Real Ci = sC[q0][i][pos];
         G.grs += K.rA[i] * gx;
         G.gys += K.rA[i] * gy;
         G.Fxs += Ci * gx;
@@ -441,19 +534,19 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
     Real phi[M], Cv[M], gpx[M], gpy[M], gCx[M], gCy[M];
     if constexpr (!kTwoHop) {
       // eq:N31a on D2Q9: d/dx = [4 (E - W) + (NE - NW + SE - SW)] / 12
-      auto grad = [&](const Real (*f)[M][kBW], int r0, int rN, int rS, int i, Real &gx,
+      auto grad = [&](const Real (*f)[M][kRW], int r0, int rN, int rS, int i, Real &gx,
                       Real &gy) {
-        const Real e = f[r0][i][lane + 1], w = f[r0][i][lane - 1];
-        const Real n = f[rN][i][lane], s = f[rS][i][lane];
-        const Real ne = f[rN][i][lane + 1], nw = f[rN][i][lane - 1];
-        const Real se = f[rS][i][lane + 1], sw = f[rS][i][lane - 1];
+        const Real e = f[r0][i][pos + 1], w = f[r0][i][pos - 1];
+        const Real n = f[rN][i][pos], s = f[rS][i][pos];
+        const Real ne = f[rN][i][pos + 1], nw = f[rN][i][pos - 1];
+        const Real se = f[rS][i][pos + 1], sw = f[rS][i][pos - 1];
         gx = (Real(4) * (e - w) + ((ne - nw) + (se - sw))) * (Real(1) / Real(12));
         gy = (Real(4) * (n - s) + ((ne + nw) - (se + sw))) * (Real(1) / Real(12));
       };
 #pragma unroll
       for (int i = 0; i < M; ++i) {
-        phi[i] = sphi[p0][i][lane];
-        Cv[i] = sC[q0][i][lane];
+        phi[i] = sphi[p0][i][pos];
+        Cv[i] = sC[q0][i][pos];
         grad(sphi, p0, pN, pS, i, gpx[i], gpy[i]);
         if constexpr (!kR1) grad(sC, q0, qN, qS, i, gCx[i], gCy[i]);
       }
@@ -462,8 +555,8 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
       const int qN2 = ring<kCR>(mC + 2 * dir), qS2 = ring<kCR>(mC - 2 * dir);
 #pragma unroll
       for (int i = 0; i < M; ++i) {
-        phi[i] = sphi[p0][i][lane];
-        Cv[i] = sC[q0][i][lane];
+        phi[i] = sphi[p0][i][pos];
+        Cv[i] = sC[q0][i][pos];
         grad2(sC, q0, qN, qS, qN2, qS2, i, gCx[i], gCy[i]);
       }
     }
@@ -508,15 +601,15 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
       const int sN = ghost(mC + dir) ? s0 : ring<kQR>(mC + dir);
       const int sS = ghost(mC - dir) ? s0 : ring<kQR>(mC - dir);
       auto ddx = [&](int c) {
-        return (Acc(4) * (sQ[s0][c][lane + 1] - sQ[s0][c][lane - 1]) +
-                ((sQ[sN][c][lane + 1] - sQ[sN][c][lane - 1]) +
-                 (sQ[sS][c][lane + 1] - sQ[sS][c][lane - 1]))) *
+        return (Acc(4) * (sQ[s0][c][pos + 1] - sQ[s0][c][pos - 1]) +
+                ((sQ[sN][c][pos + 1] - sQ[sN][c][pos - 1]) +
+                 (sQ[sS][c][pos + 1] - sQ[sS][c][pos - 1]))) *
                (Acc(1) / Acc(12));
       };
       auto ddy = [&](int c) {
-        return (Acc(4) * (sQ[sN][c][lane] - sQ[sS][c][lane]) +
-                ((sQ[sN][c][lane + 1] + sQ[sN][c][lane - 1]) -
-                 (sQ[sS][c][lane + 1] + sQ[sS][c][lane - 1]))) *
+        return (Acc(4) * (sQ[sN][c][pos] - sQ[sS][c][pos]) +
+                ((sQ[sN][c][pos + 1] + sQ[sN][c][pos - 1]) -
+                 (sQ[sS][c][pos + 1] + sQ[sS][c][pos - 1]))) *
                (Acc(1) / Acc(12));
       };
       Fx -= ddx(0) + ddy(1);
@@ -701,19 +794,23 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
     }
   } else if constexpr (kPipeline) {
     Pulled<M, Real> bufA, bufB, bufC;
+    Real hv[kHP];  // halo values of row mA, pulled with its CH populations
     auto iteration = [&](int j, const Pulled<M, Real> &cur, Pulled<M, Real> &next,
                          const Pulled<M, Real> &held) {
       const int mA = 2 * j - kRamp + ry;
       stageA(mA, cur);
+      halo_phi(mA, hv);
       __syncthreads();
       pull_ns(mA - kLag, ns);
       const PhiGrad g1 = stageG(mA - kLag);
       pull_ch(mA + 2, next);
+      halo_pull(mA + 2, hv);
       stageB(mA - 1);
       __syncthreads();
       stageC(mA - kLag, held, ns, g1);
     };
     pull_ch(ry - kRamp, bufA);
+    halo_pull(ry - kRamp, hv);
     for (int j = 0; j < J; j += 3) {  // j is uniform over the block
       iteration(j, bufA, bufB, bufC);
       if (j + 1 < J) iteration(j + 1, bufB, bufC, bufA);
@@ -721,10 +818,13 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
     }
   } else {
     Pulled<M, Real> bufA, bufB;  // pulled for mA (cur) and for mA - 2 (held)
+    Real hv[kHP];
     auto iteration = [&](int j, Pulled<M, Real> &cur, const Pulled<M, Real> &held) {
       const int mA = 2 * j - kRamp + ry;
       pull_ch(mA, cur);
+      halo_pull(mA, hv);
       stageA(mA, cur);
+      halo_phi(mA, hv);
       __syncthreads();
       pull_ns(mA - kLag, ns);
       const PhiGrad g1 = stageG(mA - kLag);
@@ -747,14 +847,15 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
 #define NPL_GS 0
 #endif
 
-// LDS of one workgroup: the phi and C rings of (N-1) x BW values, plus the
-// product and velocity rings of the Remark 1 scheme
+// LDS of one workgroup: the phi and C rings of (N-1) x row-width values
+// (rows of interior lanes have kBW + 4 columns), plus the product and
+// velocity rings of the Remark 1 scheme
 constexpr int lds_bytes(int N, int bytes, int bw, int gs) {
   return ((gs == 1 ? Scheme<1>::kPR + Scheme<1>::kCR
                    : (gs == 2 ? Scheme<2>::kPR + Scheme<2>::kCR : Scheme<0>::kPR + Scheme<0>::kCR)) *
               (N - 1) +
           (gs == 2 ? 4 * kQR + 2 * kUR : 0)) *
-         bw * bytes;
+         (interior_lanes(N, bytes, gs) ? bw + 2 * Scheme<0>::kHalo : bw) * bytes;
 }
 // LDS budget of a workgroup: 64 KiB for the central scheme; 80 KiB for the
 // others (gfx950 has 160 KiB per CU, so two such workgroups still fit)
