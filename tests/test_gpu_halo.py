@@ -1,0 +1,70 @@
+"""The x-halo of the central-scheme step kernel, where each lane of a row owns
+an interior column and the phi of the four halo columns is pulled one lane
+per (halo node, direction) (FP32 for N <= 5, FP64 for N <= 3).
+
+- FP64 against the oracle (1e-10 max-abs on c, u, p) on lattices narrower
+  than the halo itself (nx = 4, 5: the halo columns wrap onto the strip's
+  own columns), a one-column strip next to a full one (nx = 33 cut into
+  strips of 32 and 1 columns), and with walls, where the halo lanes of
+  the rows next to a wall take the bounce-back sources;
+- FP32 and FP64 states bitwise identical across strip widths (256, 32, 8
+  columns: every strip edge moves), so a halo phi equals, bit for bit, the
+  phi the neighbouring strip computes for that node.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.accept import oracle_accepts
+from tests.gpu_util import gpu_domain, maxabs, oracle_run
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+KEYS = ("NPLBM_TX",)
+
+
+def _state(w, precision, steps, env):
+    saved = {k: os.environ.pop(k, None) for k in KEYS}
+    os.environ.update(env)
+    try:
+        d = gpu_domain(w, precision=precision)
+        d.step(steps)
+        out = [np.asarray(a) for a in d.macro()]
+        d.close()
+    finally:
+        for k in KEYS:
+            os.environ.pop(k, None)
+            if saved[k] is not None:
+                os.environ[k] = saved[k]
+    return out
+
+
+@pytest.mark.parametrize("N,nx,ny,wall,tx", [
+    (3, 4, 9, False, None),
+    (2, 5, 12, True, None),
+    (3, 33, 6, True, "32"),
+    (3, 33, 7, False, "32"),
+    (2, 70, 10, True, "8"),
+])
+def test_halo_lanes_fp64_against_oracle(N, nx, ny, wall, tx):
+    w = W.random_smooth(N, nx, ny, seed=9100 + nx + ny, wall_y=wall, accept=oracle_accepts)
+    steps = 20
+    print(f"case halo N={N} {nx}x{ny} wall={wall} tx={tx} fp64 steps={steps}", flush=True)
+    o = oracle_run(w, steps)
+    got = _state(w, 64, steps, {"NPLBM_TX": tx} if tx else {})
+    err = [maxabs(a, b) for a, b in zip(got, o.macro())]
+    assert max(err) < TOL, err
+
+
+@pytest.mark.parametrize("precision,N", [(32, 2), (32, 3), (32, 5), (64, 2), (64, 3)])
+@pytest.mark.parametrize("wall", [False, True])
+def test_halo_lanes_bitwise_across_strip_widths(precision, N, wall):
+    w = W.random_smooth(N, 300, 23, seed=9200 + N + 10 * wall, wall_y=wall, accept=oracle_accepts)
+    print(f"case halo bitwise N={N} 300x23 wall={wall} fp{precision} steps=30", flush=True)
+    ref = _state(w, precision, 30, {})
+    for tx in ("32", "8"):
+        got = _state(w, precision, 30, {"NPLBM_TX": tx})
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b), tx
