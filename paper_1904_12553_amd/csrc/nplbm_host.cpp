@@ -447,7 +447,8 @@ Layout plan_layout(const nplbm_params *p) {
 // (32 floats or 16 doubles), so no line is written by two workgroups.  Rows
 // of 256 threads measured fastest on gfx950 in FP32, and in FP64 with the
 // central gradients for N <= 3 (4096^2: N = 2 64.7% of the HBM roofline
-// against 60.6% with 64-thread rows, N = 3 65.8% against 59.5%); FP64 with
+// against 60.6% with 64-thread rows, N = 3 65.8% against 59.5%, and 74.4%
+// once the rows became interior lanes with 256-column strips); FP64 with
 // N >= 4 or the two-hop schemes runs one wave per SIMD, where 64-thread rows
 // measured fastest (N = 4: 66.3% against 58.0%).  The mixed scheme in FP32
 // runs two 128-thread-row workgroups per compute unit instead of one with

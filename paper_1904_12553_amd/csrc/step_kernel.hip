@@ -724,9 +724,10 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   // with the CH pulls of row mA held in registers until their collision
   // kLag / 2 iterations later.
   //  - central, FP32, N <= 5: the registers allow pipelining one more set:
-  //    the CH pulls of mA + 2 are issued right after the first barrier, so
-  //    they are in flight during stages B and C (three sets rotate: cur =
-  //    mA, next = mA + 2, held = mA - 2);
+  //    the CH pulls of mA + 2 (and the x-halo values of that row) are
+  //    issued right after the first barrier, so they are in flight during
+  //    stages B and C (three sets rotate: cur = mA, next = mA + 2, held =
+  //    mA - 2);
   //  - central otherwise: two sets (cur, held = mA - 2); three would halve
   //    the occupancy or spill;
   //  - mixed and Remark 1, N <= 5: three sets (cur, mA - 2, mA - 4); the
