@@ -30,16 +30,21 @@ __device__ __forceinline__ Real bld(Rsrc r, uint32_t voff, uint32_t soff) {
   else
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
-// Stores of the new state are never read again within the step; FP64 runs
-// measured faster with them marked nontemporal (streaming), FP32 slower.
-template <typename Real>
+// Stores of the new state are never read again within the step; kNT marks
+// them nontemporal (streaming).  Measured faster wherever each wave's row
+// of stores covers whole cache lines: every FP64 kernel, the FP32 2-D rows
+// of interior lanes (2048^2 N = 5: 62.2% -> 62.9% of the HBM roofline,
+// 4096^2 N = 3: 66.9% -> 70.9%) and the D3Q15 passes (256^3 N = 3: 48.1%
+// -> 51.0%); slower on the FP32 rows that hold their halo (mixed N = 5:
+// 58.4% -> 57.1%).
+template <typename Real, bool kNT>
 __device__ __forceinline__ void bst(Rsrc r, uint32_t voff, uint32_t soff, Real v) {
   typedef unsigned u2 __attribute__((ext_vector_type(2)));
-  constexpr int kNontemporal = 2;  // cache-policy bit nt of gfx94x/gfx950
+  constexpr int kAux = kNT ? 2 : 0;  // cache-policy bit nt of gfx94x/gfx950
   if constexpr (sizeof(Real) == 8)
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, kNontemporal);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, kAux);
   else
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, kAux);
 }
 
 }  // namespace nplbm

@@ -485,8 +485,8 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
           w * (itau * (e0 + Acc(4.5) * rho * cu * cu) +
                srcg * (gbase + Acc(4.5) * cu * (Acc(2) * cF + Acc(2) / Acc(3) * cr + theta * cJ)));
       const Acc od = w * Acc(3) * (itau * rho * cu + srcg * cF);
-      bst<Real>(wg, xcu, ybg[1] + (uint32_t)(k - 1) * pb, keep * g[k] + ev + od);
-      bst<Real>(wg, xcu, ybg[1] + (uint32_t)(ko - 1) * pb, keep * g[ko] + ev - od);
+      bst<Real, true>(wg, xcu, ybg[1] + (uint32_t)(k - 1) * pb, keep * g[k] + ev + od);
+      bst<Real, true>(wg, xcu, ybg[1] + (uint32_t)(ko - 1) * pb, keep * g[ko] + ev - od);
     }
 #pragma unroll
     for (int i = 0; i < M; ++i) {
@@ -527,8 +527,8 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
         const Real hn = keep * P.h[i][k] + ev + od;
         const Real ho = keep * P.h[i][ko] + ev - od;
         hsum += hn + ho;
-        bst<Real>(wh, xcu, ybh[1] + (uint32_t)(i * 15 + k) * pb, hn);
-        bst<Real>(wh, xcu, ybh[1] + (uint32_t)(i * 15 + ko) * pb, ho);
+        bst<Real, true>(wh, xcu, ybh[1] + (uint32_t)(i * 15 + k) * pb, hn);
+        bst<Real, true>(wh, xcu, ybh[1] + (uint32_t)(i * 15 + ko) * pb, ho);
       }
       // phi_i = pp + lo exactly; fl(phi_i) is stored as the new previous
       // phi and the k = 0 slot keeps (pp + lo - fl(phi_i)) - sum h_k
@@ -537,11 +537,11 @@ __global__ void __launch_bounds__(k3W * TY) k_step3(StepArgs a) {
       for (int k = 1; k < 15; ++k) lo += P.h[i][k];
       const Real bb = phii - pp;
       const Real err = (pp - (phii - bb)) + (lo - bb);
-      bst<Real>(wh, xcu, ybh[1] + (uint32_t)(i * 15) * pb, err - hsum);
-      bst<Real>(wp, xcu, ybp + (uint32_t)i * pb, phii);
+      bst<Real, true>(wh, xcu, ybh[1] + (uint32_t)(i * 15) * pb, err - hsum);
+      bst<Real, true>(wp, xcu, ybp + (uint32_t)i * pb, phii);
     }
 #pragma unroll
-    for (int d = 0; d < 3; ++d) bst<Real>(wp, xcu, ybp + (uint32_t)(M + d) * pb, u[d]);
+    for (int d = 0; d < 3; ++d) bst<Real, true>(wp, xcu, ybp + (uint32_t)(M + d) * pb, u[d]);
   };
 
   // March: iteration j pulls plane mA = j - 2, computes C of mA - 1 and
@@ -634,7 +634,7 @@ __global__ void __launch_bounds__(256) k_phi3(StepArgs a) {
   }
   const Rsrc wf = row_rsrc(D->phi3, (uint32_t)ny * rbf, z);
 #pragma unroll
-  for (int i = 0; i < M; ++i) bst<Real>(wf, xcu, (uint32_t)y * rbf + (uint32_t)i * pb, f[i]);
+  for (int i = 0; i < M; ++i) bst<Real, true>(wf, xcu, (uint32_t)y * rbf + (uint32_t)i * pb, f[i]);
 }
 
 template <int N, int TY>

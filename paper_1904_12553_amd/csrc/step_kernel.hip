@@ -178,6 +178,8 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   // x0 - kHalo + l, and the halo lanes pull their nodes like the interior
   // ones and do not collide.
   constexpr bool kIL = interior_lanes(N, sizeof(Real), kGS);
+  // nontemporal stores of the new state (see bst)
+  constexpr bool kNTS = sizeof(Real) == 8 || kIL;
   constexpr int kRW = kIL ? kBW + 2 * kHalo : kBW;  // ring row width
   __shared__ Real sphi[kPR][M][kRW];
   __shared__ Real sC[kCR][M][kRW];
@@ -674,8 +676,8 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
                                    (Acc(2) * cF + Acc(2) / Acc(3) * cr +
                                     (kR1 ? Acc(0) : theta * cJ))));
       const Acc od = w * Acc(3) * (itau * rho * cu + srcg * cF);
-      bst<Real>(wg, xcu, (uint32_t)(k - 1) * pb, keep * g[k] + ev + od);
-      bst<Real>(wg, xcu, (uint32_t)(ko - 1) * pb, keep * g[ko] + ev - od);
+      bst<Real, kNTS>(wg, xcu, (uint32_t)(k - 1) * pb, keep * g[k] + ev + od);
+      bst<Real, kNTS>(wg, xcu, (uint32_t)(ko - 1) * pb, keep * g[ko] + ev - od);
     }
     // CH collisions
     const Real pux = Q.pu[0], puy = Q.pu[1];
@@ -702,8 +704,8 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
         const Real hn = keep * P.h[i][k] + ev + od;
         const Real ho = keep * P.h[i][ko] + ev - od;
         hsum += hn + ho;
-        bst<Real>(wh, xcu, (uint32_t)(i * 9 + k) * pb, hn);
-        bst<Real>(wh, xcu, (uint32_t)(i * 9 + ko) * pb, ho);
+        bst<Real, kNTS>(wh, xcu, (uint32_t)(i * 9 + k) * pb, hn);
+        bst<Real, kNTS>(wh, xcu, (uint32_t)(i * 9 + ko) * pb, ho);
       }
       // phi_i = hi + lo exactly; phi[i] = fl(hi + lo) is stored as the new
       // previous phi and the k = 0 slot keeps (hi + lo - phi[i]) - sum h_k
@@ -711,11 +713,11 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
       const Real lo = lo_sum(P.h[i]);
       const Real bb = phi[i] - pp;
       const Real err = (pp - (phi[i] - bb)) + (lo - bb);
-      bst<Real>(wh, xcu, (uint32_t)(i * 9) * pb, err - hsum);
-      bst<Real>(wp, xcu, (uint32_t)i * pb, phi[i]);
+      bst<Real, kNTS>(wh, xcu, (uint32_t)(i * 9) * pb, err - hsum);
+      bst<Real, kNTS>(wp, xcu, (uint32_t)i * pb, phi[i]);
     }
-    bst<Real>(wp, xcu, (uint32_t)M * pb, ux);
-    bst<Real>(wp, xcu, (uint32_t)(M + 1) * pb, uy);
+    bst<Real, kNTS>(wp, xcu, (uint32_t)M * pb, ux);
+    bst<Real, kNTS>(wp, xcu, (uint32_t)(M + 1) * pb, uy);
   };
 
   // March over iterations j (march index mA = 2j - kRamp + row).  Each does
