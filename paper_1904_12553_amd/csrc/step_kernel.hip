@@ -170,7 +170,8 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
                  rbp = (uint32_t)D->rs[2] * SZ;
 
   // Lane layout.  Interior lanes (interior_lanes: the central scheme at
-  // N <= 5 in FP32, N <= 3 in FP64): lane l owns interior column x0 + l,
+  // N <= 5 in FP32, N <= 3 in FP64, the mixed scheme at N <= 5 in FP32):
+  // lane l owns interior column x0 + l,
   // ring column l + kHalo, so a strip has up to kBW interior columns and
   // every row of loads and stores starts on the strip's first cache line;
   // phi of the 2 kHalo halo columns is pulled one lane per (halo node,
@@ -306,9 +307,10 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
     }
   };
 
-  // ---- x-halo phi of the central scheme ----
-  // Phase i of the kNH halo nodes of a row (columns x0 - 2, x0 - 1, x1,
-  // x1 + 1) is pulled by one wave of the row: lane t < 9 kNH pulls
+  // ---- x-halo phi of rows of interior lanes ----
+  // Phase i of the kNH halo nodes of a row (columns x0 - kHalo .. x0 - 1
+  // and x1 .. x1 + kHalo - 1) is pulled by one wave of the row: lane
+  // t < 9 kNH pulls
   // direction t % 9 of halo node t / 9 and lane 9 kNH + n the stored phi of
   // node n, so a phase costs one load instruction instead of the 9 of a
   // lane per node.  The row's waves share the phases (the wave wv of the
@@ -320,36 +322,53 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   constexpr int kHP = kIL ? (M + kNW - 1) / kNW : 1;  // phases per wave
   __shared__ Real shalo[kIL ? kRows * kNW : 1][10 * kNH];
   const int wv = __builtin_amdgcn_readfirstlane((threadIdx.x % kBW) / 64);  // wave in the row
+  // Per-lane halo descriptor, decoded at each pull (kept in one register
+  // through the march): the halo node's column (bits 0..26) and its
+  // direction + 1 (bits 27..30; 0: stored phi, 15: lane without a value).
+  uint32_t hdesc = 15u << 27;
+  if constexpr (kIL) {
+    const int wl = threadIdx.x & 63;  // lane in the wave
+    if (wl < 10 * kNH) {
+      const int hn = wl < 9 * kNH ? wl / 9 : wl - 9 * kNH;  // halo node of this lane
+      const int hk = wl < 9 * kNH ? wl % 9 : -1;           // its direction (-1: stored phi)
+      int hxc = (hn < kHalo ? sd.x0 - kHalo + hn : sd.x1 + hn - kHalo) % nx;
+      if (hxc < 0) hxc += nx;
+      hdesc = (uint32_t)hxc | ((uint32_t)(hk + 1) << 27);
+    }
+  }
   auto halo_pull = [&](int m, Real (&hv)[kHP]) {
     if constexpr (kIL) {
       const int yp = phys_row(row_of(m));
-      const int wl = threadIdx.x & 63;  // lane in the wave
-      if (wl < 10 * kNH) {
-        const int hn = wl < 9 * kNH ? wl / 9 : wl - 9 * kNH;  // halo node of this lane
-        const int hk = wl < 9 * kNH ? wl % 9 : -1;           // its direction (-1: stored phi)
-        int hxc = (hn < kHalo ? sd.x0 - kHalo + hn : sd.x1 + hn - kHalo) % nx;
-        if (hxc < 0) hxc += nx;
-        // source node and direction (bounce-back beyond a wall), as src_of
-        int sy = yp, sx = hxc, kk = hk;
-        if (hk > 0) {
-          const int cx = cxk(hk), cy = cyk(hk);
-          const int ys = yp - cy;
-          if (wall && (ys < 0 || ys >= ny)) {
-            kk = oppk(hk);
-          } else {
-            sy = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
-            sx = hxc - cx;
-            sx = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
-          }
+      // decode here, not once outside the march (the mixed scheme at N = 5
+      // needs those registers): the empty asm makes dsc depend on the row
+      // (no side effects, so loads still move across it)
+      uint32_t dsc = hdesc;
+      asm("" : "+v"(dsc) : "s"(m));
+      const uint32_t hkp = dsc >> 27, hxc = dsc & ((1u << 27) - 1);
+      // source node and direction hkp - 1 (bounce-back beyond a wall), as
+      // src_of
+      int sy = yp, sx = (int)hxc, kk = (int)hkp - 1;
+      if (hkp >= 2 && hkp <= 9) {
+        const int k = (int)hkp - 1;
+        const int cx = cxk(k), cy = cyk(k);
+        const int ys = yp - cy;
+        if (wall && (ys < 0 || ys >= ny)) {
+          kk = oppk(k);
+        } else {
+          sy = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
+          sx -= cx;
+          sx = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
         }
-        typedef const __attribute__((address_space(1))) char GC;
-        GC *base = hk >= 0 ? (GC *)hs + (size_t)sy * rbh + (size_t)sx * SZ
-                           : (GC *)pvs + (size_t)yp * rbp + (size_t)hxc * SZ;
+      }
+      typedef const __attribute__((address_space(1))) char GC;
+      GC *base = hkp != 0 ? (GC *)hs + (size_t)sy * rbh + (size_t)sx * SZ
+                          : (GC *)pvs + (size_t)yp * rbp + (size_t)hxc * SZ;
+      if (hkp <= 9) {
 #pragma unroll
         for (int q = 0; q < kHP; ++q) {
           const int i = wv + q * kNW;
           if (i < M) {
-            const uint32_t plane = hk >= 0 ? (uint32_t)(i * 9 + kk) : (uint32_t)i;
+            const uint32_t plane = hkp != 0 ? (uint32_t)(i * 9 + kk) : (uint32_t)i;
             hv[q] = *(const __attribute__((address_space(1))) Real *)(base + (size_t)plane * pb);
           }
         }
@@ -432,9 +451,9 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
       }
     };
     if constexpr (kIL) {
-      // ring columns 1 .. ncol + 2: lane l takes l + 1, and lanes 0 and 1
-      // also the last two of a full-width strip
-      for (int x = lane + 1; x <= ncol + 2; x += kBW) chem(x);
+      // ring columns 1 .. ncol + 2 kHalo - 2: lane l takes l + 1, and the
+      // first lanes also the last 2 kHalo - 2 of a full-width strip
+      for (int x = lane + 1; x <= ncol + 2 * kHalo - 2; x += kBW) chem(x);
     } else {
       if (lane >= 1 && lane <= ncol + 2 * kHalo - 2) chem(pos);
     }
@@ -775,10 +794,13 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
     }
   } else if constexpr (kGS != 0) {
     Pulled<M, Real> bufA, bufB, bufC;
+    Real hv[kHP];
     auto iteration = [&](int j, Pulled<M, Real> &cur, const Pulled<M, Real> &held) {
       const int mA = 2 * j - kRamp + ry;
       pull_ch(mA, cur);
+      halo_pull(mA, hv);
       stageA(mA, cur);
+      halo_phi(mA, hv);
       __syncthreads();
       pull_ns(mA - kLag, ns);
       const PhiGrad g1 = stageG(mA - kLag);
@@ -858,7 +880,8 @@ constexpr int lds_bytes(int N, int bytes, int bw, int gs) {
                    : (gs == 2 ? Scheme<2>::kPR + Scheme<2>::kCR : Scheme<0>::kPR + Scheme<0>::kCR)) *
               (N - 1) +
           (gs == 2 ? 4 * kQR + 2 * kUR : 0)) *
-         (interior_lanes(N, bytes, gs) ? bw + 2 * Scheme<0>::kHalo : bw) * bytes;
+         (interior_lanes(N, bytes, gs) ? bw + 2 * (gs ? Scheme<1>::kHalo : Scheme<0>::kHalo) : bw) *
+         bytes;
 }
 // LDS budget of a workgroup: 64 KiB for the central scheme; 80 KiB for the
 // others (gfx950 has 160 KiB per CU, so two such workgroups still fit)
