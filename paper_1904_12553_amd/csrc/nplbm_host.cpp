@@ -450,18 +450,19 @@ Layout plan_layout(const nplbm_params *p) {
 // against 60.6% with 64-thread rows, N = 3 65.8% against 59.5%, and 74.4%
 // once the rows became interior lanes with 256-column strips); FP64 with
 // N >= 4 or the two-hop schemes runs one wave per SIMD, where 64-thread rows
-// measured fastest (N = 4: 66.3% against 58.0%).  The mixed scheme in FP32
-// runs two 128-thread-row workgroups per compute unit instead of one with
-// 256-thread rows (2048^2: N = 4 55.4% against 52.8%, N = 5 58.2% against
-// 54.6%, N = 3 equal).  The halo is 2 columns for the central gradients and
-// 3 for the two-hop ones (eq:N40, or the divergence of Remark 1 taken of a
-// product of gradients).
+// measured fastest (N = 4: 66.3% against 58.0%).  The two-hop schemes in
+// FP32 run two 128-thread-row workgroups per compute unit instead of one
+// with 256-thread rows (mixed, rows of interior lanes, 2048^2: N = 3 62.4%
+// against 57.4%, N = 4 60.4% against 54.9%, N = 5 61.2% against 56.3%;
+// Remark 1 at N >= 4 has LDS rings for no more than 128).  The halo is 2
+// columns for the central gradients and 3 for the two-hop ones (eq:N40, or
+// the divergence of Remark 1 taken of a product of gradients).
 StepGeom step_geom(int N, int precision, int scheme) {
   StepGeom g;
   g.halo = scheme == kSchemeCentral ? 2 : 3;
   const int unit = precision == 64 ? 16 : 32;
   g.bw = precision == 64 ? (scheme == kSchemeCentral && N <= 3 ? 256 : 64)
-                         : (scheme == kSchemeMixed ? 128 : 256);
+                         : (scheme == kSchemeCentral ? 256 : 128);
   if (const char *e = std::getenv("NPLBM_BW")) {
     const int b = std::atoi(e);
     g.bw = (b == 128 || b == 256) ? b : 64;

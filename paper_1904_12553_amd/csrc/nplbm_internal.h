@@ -33,13 +33,13 @@ constexpr int kSchemeRemark1 = 2;
 // Whether every lane of a step-kernel row owns an interior column (the
 // x-halo phi then comes from lanes that each pull one population of a halo
 // node): the central scheme in FP32 for N <= 5 and in FP64 for N <= 3, the
-// mixed scheme in FP32 for N <= 5.  Elsewhere the rows hold their halo
-// columns: with more phases the extra registers of the halo pull cost more
-// than the wider strips gain (FP64 N = 7 spilled), and the Remark 1 scheme
-// would also need the halo nodes' previous velocity.
+// mixed and Remark 1 schemes in FP32 for N <= 5.  Elsewhere the rows hold
+// their halo columns: with more phases, or in FP64 with the two-hop
+// schemes, the extra registers of the halo pull cost more than the wider
+// strips gain (FP64 N = 7 spilled).
 constexpr bool interior_lanes(int N, int bytes, int scheme) {
   return (scheme == kSchemeCentral && N <= (bytes == 4 ? 5 : 3)) ||
-         (scheme == kSchemeMixed && bytes == 4 && N <= 5);
+         (scheme != kSchemeCentral && bytes == 4 && N <= 5);
 }
 // Geometry used for N phases at a precision (32 / 64) and scheme;
 // NPLBM_BW and NPLBM_TX override.

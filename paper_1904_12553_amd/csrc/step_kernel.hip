@@ -170,8 +170,8 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
                  rbp = (uint32_t)D->rs[2] * SZ;
 
   // Lane layout.  Interior lanes (interior_lanes: the central scheme at
-  // N <= 5 in FP32, N <= 3 in FP64, the mixed scheme at N <= 5 in FP32):
-  // lane l owns interior column x0 + l,
+  // N <= 5 in FP32, N <= 3 in FP64, the two-hop schemes at N <= 5 in
+  // FP32): lane l owns interior column x0 + l,
   // ring column l + kHalo, so a strip has up to kBW interior columns and
   // every row of loads and stores starts on the strip's first cache line;
   // phi of the 2 kHalo halo columns is pulled one lane per (halo node,
@@ -302,8 +302,10 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
 #pragma unroll
       for (int i = 0; i < M; ++i) sphi[slot][i][pos] = cur.hi[i] + lo_sum(cur.h[i]);  // eq:N28
     if constexpr (kR1) {
-      sU[ring<kUR>(mA)][0][pos] = cur.pu[0];
-      sU[ring<kUR>(mA)][1][pos] = cur.pu[1];
+      if (!kIL || lane < ncol) {
+        sU[ring<kUR>(mA)][0][pos] = cur.pu[0];
+        sU[ring<kUR>(mA)][1][pos] = cur.pu[1];
+      }
     }
   };
 
@@ -323,17 +325,30 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   __shared__ Real shalo[kIL ? kRows * kNW : 1][10 * kNH];
   const int wv = __builtin_amdgcn_readfirstlane((threadIdx.x % kBW) / 64);  // wave in the row
   // Per-lane halo descriptor, decoded at each pull (kept in one register
-  // through the march): the halo node's column (bits 0..26) and its
-  // direction + 1 (bits 27..30; 0: stored phi, 15: lane without a value).
+  // through the march): the halo node's column (bits 0..26) and what the
+  // lane loads (bits 27..30): 0 the stored phi, 1..9 direction 0..8, 10 and
+  // 11 the stored u_x and u_y (Remark 1: J~ u is needed one column beyond
+  // the interior, so lanes 10 kNH .. 10 kNH + 3 load the previous u of
+  // the halo nodes x0 - 1 and x1, once per row), 15 nothing.
+  static_assert(!kIL || 10 * kNH + (kR1 ? 4 : 0) <= 64, "halo lanes");
   uint32_t hdesc = 15u << 27;
   if constexpr (kIL) {
     const int wl = threadIdx.x & 63;  // lane in the wave
-    if (wl < 10 * kNH) {
-      const int hn = wl < 9 * kNH ? wl / 9 : wl - 9 * kNH;  // halo node of this lane
-      const int hk = wl < 9 * kNH ? wl % 9 : -1;           // its direction (-1: stored phi)
+    int hn = -1, what = 15;           // halo node of this lane, what it loads
+    if (wl < 9 * kNH) {
+      hn = wl / 9;
+      what = wl % 9 + 1;
+    } else if (wl < 10 * kNH) {
+      hn = wl - 9 * kNH;
+      what = 0;
+    } else if (kR1 && wl < 10 * kNH + 4) {
+      hn = kHalo - 1 + (wl - 10 * kNH) / 2;
+      what = 10 + (wl - 10 * kNH) % 2;
+    }
+    if (hn >= 0) {
       int hxc = (hn < kHalo ? sd.x0 - kHalo + hn : sd.x1 + hn - kHalo) % nx;
       if (hxc < 0) hxc += nx;
-      hdesc = (uint32_t)hxc | ((uint32_t)(hk + 1) << 27);
+      hdesc = (uint32_t)hxc | ((uint32_t)what << 27);
     }
   }
   auto halo_pull = [&](int m, Real (&hv)[kHP]) {
@@ -361,17 +376,21 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
         }
       }
       typedef const __attribute__((address_space(1))) char GC;
-      GC *base = hkp != 0 ? (GC *)hs + (size_t)sy * rbh + (size_t)sx * SZ
-                          : (GC *)pvs + (size_t)yp * rbp + (size_t)hxc * SZ;
+      const bool pop = hkp >= 1 && hkp <= 9;
+      GC *base = pop ? (GC *)hs + (size_t)sy * rbh + (size_t)sx * SZ
+                     : (GC *)pvs + (size_t)yp * rbp + (size_t)hxc * SZ;
+      typedef const __attribute__((address_space(1))) Real GR;
       if (hkp <= 9) {
 #pragma unroll
         for (int q = 0; q < kHP; ++q) {
           const int i = wv + q * kNW;
           if (i < M) {
-            const uint32_t plane = hkp != 0 ? (uint32_t)(i * 9 + kk) : (uint32_t)i;
-            hv[q] = *(const __attribute__((address_space(1))) Real *)(base + (size_t)plane * pb);
+            const uint32_t plane = pop ? (uint32_t)(i * 9 + kk) : (uint32_t)i;
+            hv[q] = *(GR *)(base + (size_t)plane * pb);
           }
         }
+      } else if (kR1 && hkp <= 11 && wv == 0) {
+        hv[0] = *(GR *)(base + (size_t)(M + hkp - 10) * pb);
       }
     }
   };
@@ -392,6 +411,13 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
             sphi[slot][i][wl < kHalo ? wl : ncol + wl] = sh[9 * kNH + wl] + lo;  // eq:N28
           }
         }
+      }
+      if constexpr (kR1) {
+        // previous u of the halo nodes x0 - 1 and x1 (ring columns kHalo - 1
+        // and ncol + kHalo)
+        const int t = wl - 10 * kNH;
+        if (wv == 0 && t >= 0 && t < 4)
+          sU[ring<kUR>(mA)][t & 1][t < 2 ? kHalo - 1 : ncol + kHalo] = hv[0];
       }
     }
   };
@@ -465,30 +491,38 @@ __global__ void __launch_bounds__(kBW * kRows) NPL_KERNEL_ATTR k_step(StepArgs a
   // beyond a wall are not evaluated: stage C reads the mirrored row, the
   // same values (the ghost of a field is its mirror image).
   auto stageJ = [&](int mJ) {
-    if (lane < 2 || lane > ncol + 2 * kHalo - 3) return;
     if (wall) {
       const int r = row_of(mJ);
       if (r < 0 || r >= ny) return;
     }
     const int q0 = ring<kCR>(mJ), qN = ring<kCR>(mJ + dir), qS = ring<kCR>(mJ - dir);
-    Real Jx = Real(0), Jy = Real(0);
-#pragma unroll
-    for (int i = 0; i < M; ++i) {
-      const Real e = sC[q0][i][pos + 1], w = sC[q0][i][pos - 1];
-      const Real n = sC[qN][i][pos], s = sC[qS][i][pos];
-      const Real ne = sC[qN][i][pos + 1], nw = sC[qN][i][pos - 1];
-      const Real se = sC[qS][i][pos + 1], sw = sC[qS][i][pos - 1];
-      const Real gx = (Real(4) * (e - w) + ((ne - nw) + (se - sw))) * (Real(1) / Real(12));
-      const Real gy = (Real(4) * (n - s) + ((ne + nw) - (se + sw))) * (Real(1) / Real(12));
-      Jx += K.Jc[i] * gx;
-      Jy += K.Jc[i] * gy;
-    }
     const int su = ring<kUR>(mJ), sq = ring<kQR>(mJ);
-    const Real ux = sU[su][0][pos], uy = sU[su][1][pos];
-    sQ[sq][0][pos] = Jx * ux;
-    sQ[sq][1][pos] = Jy * ux;
-    sQ[sq][2][pos] = Jx * uy;
-    sQ[sq][3][pos] = Jy * uy;
+    // at ring column x (2 .. ncol + 2 kHalo - 3)
+    auto prod = [&](int x) {
+      Real Jx = Real(0), Jy = Real(0);
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        const Real e = sC[q0][i][x + 1], w = sC[q0][i][x - 1];
+        const Real n = sC[qN][i][x], s = sC[qS][i][x];
+        const Real ne = sC[qN][i][x + 1], nw = sC[qN][i][x - 1];
+        const Real se = sC[qS][i][x + 1], sw = sC[qS][i][x - 1];
+        const Real gx = (Real(4) * (e - w) + ((ne - nw) + (se - sw))) * (Real(1) / Real(12));
+        const Real gy = (Real(4) * (n - s) + ((ne + nw) - (se + sw))) * (Real(1) / Real(12));
+        Jx += K.Jc[i] * gx;
+        Jy += K.Jc[i] * gy;
+      }
+      const Real ux = sU[su][0][x], uy = sU[su][1][x];
+      sQ[sq][0][x] = Jx * ux;
+      sQ[sq][1][x] = Jy * ux;
+      sQ[sq][2][x] = Jx * uy;
+      sQ[sq][3][x] = Jy * uy;
+    };
+    if constexpr (kIL) {
+      // lane l takes column l + 2, and the first lanes also the last two
+      for (int x = lane + 2; x <= ncol + 2 * kHalo - 3; x += kBW) prod(x);
+    } else {
+      if (lane >= 2 && lane <= ncol + 2 * kHalo - 3) prod(pos);
+    }
   };
 
   // ---- stage G (mixed scheme): the phi gradients of march index mC ----
