@@ -4,8 +4,11 @@
 // One launch advances every node of every listed domain by one time step.
 // Work decomposition: a workgroup owns a strip of interior columns and
 // [y0, y1) rows and marches along y, two rows per iteration (one row of
-// kBW lanes per march row: the interior columns plus a halo on each side).
-// Per iteration, with march index m counted from the strip start:
+// kBW lanes per march row: one lane per interior column, the phi of the
+// halo columns pulled one lane per population; or, for FP64 with N >= 4
+// or the two-hop schemes and for N >= 6, the interior columns plus halo
+// lanes on each side).  Per iteration, with march index m counted from the
+// strip start:
 //
 //   stage A (rows m, m+1): pull the 9(N-1) CH populations from the
 //            neighbours (streaming fused into the load), phi_i = sum_k h
