@@ -45,20 +45,30 @@ def test_bands_2048_fp32_vs_fp64():
     assert np.all(np.isfinite(m0))
 
 
-def test_sphere_256cubed_parity():
-    """The D3Q15 benchmark workload (N = 3 sphere, 256^3) in the launch
-    configuration the benchmark times: FP64 GPU against the 3-D oracle after
-    one step, the window the oracle finishes in seconds at this size."""
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("which,checkpoints", [("sphere", [1, 20, 60]), ("slabs", [8, 24])])
+def test_256cubed_parity(which, checkpoints):
+    """The D3Q15 benchmark workloads (the N = 3 sphere and the N = 5 slabs
+    and spheres, 256^3) in the launch configuration the benchmark times:
+    FP64 GPU against the 3-D oracle after 1, 20 and 60 steps (sphere; the
+    runs replay graphs of 16 and 4, 32 and 8 steps) and 8 and 24 steps
+    (slabs), windows the oracle finishes in about a minute each at this
+    size on 16 host threads."""
     from oracle import OracleSim3D
-    w = W.static_sphere(256, R=64.0)
-    print(f"case {w.name} 256^3 steps=1", flush=True)
+    w = (W.static_sphere(256, R=64.0) if which == "sphere"
+         else W.slabs_and_spheres(256, accept=oracle_accepts))
     o = OracleSim3D(**w.params())
     o.init(w.c, w.u)
-    o.step(1)
     d = gpu_domain(w, precision=64)
-    d.step(1)
-    for a, b in zip(d.macro(), o.macro()):
-        assert maxabs(a, b) < TOL
+    t = 0
+    for cp in checkpoints:
+        print(f"case {w.name} 256^3 N={w.N} steps={cp}", flush=True)
+        o.step(cp - t)
+        d.step(cp - t)
+        t = cp
+        err = max(maxabs(a, b) for a, b in zip(d.macro(), o.macro()))
+        print(f"  t={t}: max |GPU - oracle| = {err:.2e}", flush=True)
+        assert err < TOL
     d.close()
 
 
